@@ -1,0 +1,231 @@
+/*
+ * gsc.h - generalized shifted COCG on MI355X (gfx950), C ABI.
+ *
+ * Solves the family of complex-symmetric sparse systems
+ *
+ *     (z_k S - H) x_k = b,        k = 0 .. nshift-1,
+ *
+ * for a real symmetric tight-binding Hamiltonian H and a real symmetric
+ * positive-definite overlap S that share one block-sparse pattern (the
+ * non-orthogonal problem of Sec. 3.1, eqs. base-2 and GreensFunc, written for
+ * a general overlap).  One seed COCG process per right-hand side (Sec. 3.3,
+ * eqs. CGp:p, CGp:x, CGp:r, S^{-1} r by an inner CG) carries every other shift
+ * through the scalar recurrence of eq. Shift:pi and the collinear residual
+ * theorem (eq. Collinear); when the seed converges the seed is switched
+ * (Sec. 3.3, seed switching) without discarding the Krylov history.
+ *
+ * Conventions shared by every entry point
+ *  - Complex numbers are interleaved (re, im) pairs of double.
+ *  - The pattern is block-CSR with B x B blocks (B = 4 or 6): rowptr has
+ *    nbrows+1 int64 entries, colidx int32 column-block indices sorted inside
+ *    each block row, both triangles stored, every diagonal block present.
+ *    Block values are row-major inside the block: val[(b*B + i)*B + j].
+ *    N = nbrows * B orbitals.
+ *  - gsc_mem says where a pointer lives: GSC_MEM_HOST (pageable host memory)
+ *    or GSC_MEM_DEVICE (device memory of the context's device).  Small
+ *    inputs (shifts, weights, index lists) are always host memory.
+ *  - The caller owns every buffer it passes; the library never frees or
+ *    keeps caller pointers beyond the call.  Device work is enqueued on the
+ *    context's stream; an entry point returns after its outputs are complete
+ *    (it synchronises the stream before returning).
+ *  - Every entry point returns a gsc_status.  Negative values are hard
+ *    errors (outputs undefined; gsc_last_error() describes the failure).
+ *    GSC_NOT_CONVERGED is positive: all outputs are written, together with
+ *    per-(shift, rhs) residual estimates and convergence flags in gsc_stats.
+ *    Arguments are validated before any device work is launched.
+ */
+#ifndef GSC_H
+#define GSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GSC_OK = 0,
+    GSC_NOT_CONVERGED = 1,
+    GSC_E_ARG = -1,          /* invalid argument / malformed pattern        */
+    GSC_E_NOMEM = -2,        /* device allocation failed                    */
+    GSC_E_DEVICE = -3,       /* HIP runtime error                           */
+    GSC_E_BREAKDOWN = -4,    /* COCG breakdown: p^T A p or r'^T r vanished  */
+    GSC_E_S_NOT_SPD = -5,    /* inner CG met d^H S d <= 0                    */
+    GSC_E_NAN = -6,          /* non-finite value in inputs or iterates      */
+    GSC_E_UNSUPPORTED = -7
+} gsc_status;
+
+typedef enum { GSC_FP64 = 0, GSC_MIXED = 1 } gsc_precision;
+typedef enum { GSC_CARRY_FULL = 0, GSC_CARRY_PROJECTED = 1 } gsc_carry;
+typedef enum { GSC_MEM_HOST = 0, GSC_MEM_DEVICE = 1 } gsc_mem;
+
+typedef struct gsc_ctx gsc_ctx;
+typedef struct gsc_pair gsc_pair;
+
+/* Solver options; gsc_opts_default() fills the defaults given in brackets. */
+typedef struct {
+    double tol;            /* [1e-10] stop shift k of rhs r once
+                              ||r_n|| / (|pi^k_n| ||b||) <= tol (Sec. 3.3,
+                              eq. Collinear: the shifted residual is r_n/pi)  */
+    int max_iter;          /* [5000] outer iterations                          */
+    double inner_tol;      /* [0 = max(1e-2 tol, 1e-15)] relative residual of
+                              the inner CG for S r' = r                        */
+    int inner_max_iter;    /* [200]                                            */
+    int precision;         /* [GSC_FP64] GSC_MIXED: complex64 vectors and
+                              products, FP64 scalars, dots and reductions      */
+    int carry;             /* [GSC_CARRY_FULL] keep x^k, p^k as full vectors;
+                              GSC_CARRY_PROJECTED keeps c^T x^k only and
+                              replaces seed switching by a collinear restart   */
+    int seed_index;        /* [-1] initial seed shift; -1 = the shift whose
+                              real part is nearest the middle of the grid     */
+    int fuse_steps;        /* [0 = auto] number m of shift-update steps applied
+                              per pass over the shifted vectors (full carry)   */
+    int rhs_tile;          /* [0 = auto] right-hand sides per device tile      */
+    int recheck;           /* [0] 1: FP64 true residual of every (k, rhs) into
+                              gsc_stats.res_true (full carry only)             */
+    int reserved[8];
+} gsc_opts;
+
+/* Statistics.  The three arrays are caller-owned HOST arrays of
+ * nshift*nrhs entries laid out [k][r] (any of them may be NULL). */
+typedef struct {
+    int outer_iters;              /* largest outer iteration count of a tile  */
+    long long inner_iters;        /* inner CG steps summed over tiles          */
+    int switches;                 /* seed switches summed over rhs            */
+    int restarts;                 /* collinear restarts summed over rhs       */
+    long long shift_rhs_iters;    /* sum over iterations and rhs of the
+                                     number of active shifts                  */
+    double seconds;               /* device time of the solve                 */
+    double *res_recursive;        /* [k][r] ||r_n|| / (|pi| ||b||) at exit      */
+    double *res_true;             /* [k][r] FP64 ||b - A_k x_k|| / ||b||        */
+    unsigned char *converged;     /* [k][r] 1 if res_recursive <= tol          */
+} gsc_stats;
+
+/* ASED geometry for gsc_ased_build / gsc_ased_vjp (Sec. 2.2, eq. Hap-1).
+ * All arrays are HOST memory.  For stored block b (block row I, column
+ * block J) and the entry (a, c) inside it, the orbitals are o1 = I*B + a and
+ * o2 = J*B + c; their atoms are u = orb_atom[o1], v = orb_atom[o2] and
+ *     d = pos[v] + trans[b] - pos[u],  r = |d|.
+ * If u == v and trans[b] == 0 the two orbitals sit on one atom: S = delta,
+ * H = delta * eps.  Otherwise S_off = s0 exp(-(r - r0)/lam) ang[b][a][c],
+ * S = c S_off and H = kappa (eps[o1] + eps[o2]) / 2 * S, where the scale
+ * c = theta / (largest off-site absolute row sum of S_off) keeps S
+ * diagonally dominant.  c is computed when scale <= 0, else taken as given
+ * (held fixed for derivatives). */
+typedef struct {
+    int64_t n_atoms;
+    const double *pos;        /* [n_atoms][3]            */
+    const int32_t *orb_atom;  /* [N]                      */
+    const double *eps;        /* [N] on-site levels       */
+    const double *trans;      /* [nnzb][3]                */
+    const double *ang;        /* [nnzb][B][B]             */
+    double s0, r0, lam, kappa, theta;
+} gsc_ased_geom;
+
+/* One system of a batched solve (all pointers HOST memory unless noted). */
+typedef struct {
+    const gsc_pair *pair;
+    int nshift;
+    const double *z;          /* [nshift] complex                          */
+    int nrhs;
+    const int64_t *rhs_idx;   /* [nrhs] unit right-hand sides e_j           */
+    const double *w;          /* [nshift] quadrature weights or NULL        */
+    double *g_diag;           /* out, DEVICE: [nshift][nrhs] complex G_jj   */
+    double *q_orb;            /* out, DEVICE: [nrhs] or NULL                */
+    double *e_orb;            /* out, DEVICE: [nrhs] or NULL                */
+    gsc_stats *stats;         /* optional per-system statistics             */
+} gsc_problem;
+
+/* ---- context ------------------------------------------------------------ */
+void gsc_opts_default(gsc_opts *opts);
+/* Create a context on HIP device `device`; `hip_stream` is a borrowed
+ * hipStream_t (NULL = the null stream). */
+gsc_status gsc_create(gsc_ctx **out, int device, void *hip_stream);
+gsc_status gsc_set_stream(gsc_ctx *ctx, void *hip_stream);
+void gsc_destroy(gsc_ctx *ctx);
+/* Thread-local description of the last failure ("" if none). */
+const char *gsc_last_error(void);
+/* Library version string. */
+const char *gsc_version(void);
+
+/* ---- the H, S pair (Sec. 3.2: the non-orthogonal basis) ------------------ */
+/* Copy the pattern and the FP64 values of H and S to the device.
+ * Hval/Sval may be NULL (values set later by gsc_pair_set_values or
+ * gsc_ased_build).  GSC_E_ARG for B not in {4, 6}, unsorted or out-of-range
+ * column indices, a missing diagonal block or nnzb >= 2^31. */
+gsc_status gsc_pair_create(gsc_ctx *ctx, int block, int64_t nbrows,
+                           const int64_t *rowptr, const int32_t *colidx,
+                           const double *Hval, const double *Sval, int mem,
+                           gsc_pair **out);
+gsc_status gsc_pair_set_values(gsc_pair *pair, const double *Hval, const double *Sval, int mem);
+gsc_status gsc_pair_get_values(const gsc_pair *pair, double *Hval, double *Sval, int mem);
+/* Sizes: N, nnzb, block. */
+gsc_status gsc_pair_info(const gsc_pair *pair, int64_t *n, int64_t *nnzb, int *block);
+void gsc_pair_destroy(gsc_pair *pair);
+
+/* ---- ASED pair (Sec. 2.2, eq. Hap-1) ------------------------------------- */
+/* Evaluate S and H on the pair's pattern from the geometry.  scale <= 0:
+ * compute c and return it in *scale_out (may be NULL). */
+gsc_status gsc_ased_build(gsc_ctx *ctx, const gsc_ased_geom *geom, double scale,
+                          gsc_pair *pair, double *scale_out);
+/* Forces F = -dE/dpos from dE/dHval and dE/dSval (same block layout as the
+ * pair values, each stored entry an independent variable), with the scale c,
+ * the pattern and the angular factors held fixed.  dHval/dSval per `mem`;
+ * forces: HOST [n_atoms][3]. */
+gsc_status gsc_ased_vjp(gsc_ctx *ctx, const gsc_ased_geom *geom, double scale,
+                        const gsc_pair *pair, const double *dHval, const double *dSval,
+                        int mem, double *forces);
+
+/* ---- products (building blocks of the seed process) ---------------------- */
+/* Y = alpha_S * S X - H X for nrhs complex columns stored row-major with the
+ * columns interleaved: X[i*nrhs + r] (complex).  alpha_S is one complex
+ * scalar per column ([nrhs] complex, HOST).  X, Y per `mem`. */
+gsc_status gsc_spmm(gsc_ctx *ctx, const gsc_pair *pair, int nrhs, const double *alpha_S,
+                    const double *X, double *Y, int mem);
+
+/* ---- the shifted solve (Sec. 3.3) ---------------------------------------- */
+/* rhs: unit vectors e_{rhs_idx[r]} (rhs_idx HOST [nrhs]) or, if rhs_idx is
+ * NULL, dense columns B_dense[r][N] complex (per out_mem).
+ * Outputs (per out_mem; either may be NULL):
+ *   G_cols [nshift][nrhs][N] complex   = x_k for rhs r   (full carry only)
+ *   G_proj [nshift][nrhs][nproj] complex = (x_k)_{proj_idx[r][m]}
+ * proj_idx: HOST [nrhs][nproj] row indices (NULL when nproj == 0). */
+gsc_status gsc_solve(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const double *z,
+                     int nrhs, const int64_t *rhs_idx, const double *B_dense,
+                     const gsc_opts *opts, double *G_cols, int nproj,
+                     const int64_t *proj_idx, double *G_proj, int out_mem,
+                     gsc_stats *stats);
+
+/* Mulliken charge and band energy per orbital a = orb_idx[r] (Sec. 2.2),
+ * spin 2, quadrature weights w[k] (HOST) over E_k = Re z_k:
+ *   q_a = -(2/pi) sum_k w_k Im[(S G_k)_aa],
+ *   e_a = -(2/pi) sum_k w_k E_k Im[(S G_k)_aa],
+ *   *e_band = sum_r e_{orb_idx[r]}  (the band energy when every orbital is
+ *   listed).  q_orb, e_orb: [norb] per out_mem; e_band: HOST. */
+gsc_status gsc_mulliken_band(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const double *z,
+                             const double *w, int norb, const int64_t *orb_idx,
+                             const gsc_opts *opts, double *q_orb, double *e_orb,
+                             double *e_band, int out_mem, gsc_stats *stats);
+
+/* Backward of the full band energy E = sum_a e_a over ALL orbitals:
+ *   dH += grad_E * dE/dH_bc = -(2/pi) sum_k w_k E_k Im[(G_k S G_k)_bc]
+ *   dS += grad_E * dE/dS_bc = -(2/pi) sum_k w_k E_k Im[(G_k - z_k G_k S G_k)_bc]
+ * on the stored entries (block layout of the pair values, per `mem`).
+ * G S G b = -dx(z)/dz is carried alongside the shifted iterates, so the
+ * backward reuses the same shifted solver.  *e_band (HOST, may be NULL)
+ * receives the band energy of the same solve. */
+gsc_status gsc_band_energy_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const double *z,
+                               const double *w, double grad_E, const gsc_opts *opts,
+                               double *dHval, double *dSval, double *e_band, int mem,
+                               gsc_stats *stats);
+
+/* Many independent systems in one launch sequence (each system's shifts,
+ * rhs and outputs as in gsc_problem; projected carry, G_jj and charges). */
+gsc_status gsc_solve_batched(gsc_ctx *ctx, int nsys, const gsc_problem *problems,
+                             const gsc_opts *opts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSC_H */

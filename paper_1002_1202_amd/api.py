@@ -1,0 +1,291 @@
+"""Python binding of the gsc C ABI: argument marshalling only.
+
+Host arrays are numpy; device arrays are torch CUDA (HIP) tensors, used as
+plain device memory.  Every computation runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _ptr(a, ctype=C.c_double):
+    """Pointer to a numpy array (host) or a torch tensor (device)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        if not a.flags.c_contiguous:
+            raise ValueError("array must be C-contiguous")
+        return a.ctypes.data_as(C.POINTER(ctype))
+    if not a.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.cast(C.c_void_p(a.data_ptr()), C.POINTER(ctype))
+
+
+def _vp(a):
+    p = _ptr(a)
+    return None if p is None else C.cast(p, C.c_void_p)
+
+
+def _is_device(a) -> bool:
+    return a is not None and not isinstance(a, np.ndarray) and getattr(a, "is_cuda", False)
+
+
+def _complex_view(a):
+    """complex128 numpy array -> float64 view (interleaved re, im)."""
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a.view(np.float64)
+
+
+class Context:
+    """One device and one stream (default: torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.lib = L.load()
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream(device).cuda_stream
+            except ImportError:
+                stream = None
+        h = C.c_void_p()
+        L.check(self.lib.gsc_create(C.byref(h), device, C.c_void_p(stream) if stream else None))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            self.lib.gsc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pair:
+    """Block-sparse H, S pair on the device (copies the pattern)."""
+
+    def __init__(self, ctx: Context, block: int, rowptr, colidx, H=None, S=None):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        self.colidx = np.ascontiguousarray(colidx, dtype=np.int32)
+        mem = L.MEM_DEVICE if _is_device(H) or _is_device(S) else L.MEM_HOST
+        if mem == L.MEM_HOST:
+            H = None if H is None else np.ascontiguousarray(H, dtype=np.float64)
+            S = None if S is None else np.ascontiguousarray(S, dtype=np.float64)
+        h = C.c_void_p()
+        L.check(self.lib.gsc_pair_create(ctx.h, block, len(self.rowptr) - 1, _ptr(self.rowptr, C.c_int64),
+                                         _ptr(self.colidx, C.c_int32), _vp(H), _vp(S), mem, C.byref(h)))
+        self.h = h
+        n, nnzb, b = C.c_int64(), C.c_int64(), C.c_int()
+        L.check(self.lib.gsc_pair_info(h, C.byref(n), C.byref(nnzb), C.byref(b)))
+        self.n, self.nnzb, self.block = n.value, nnzb.value, b.value
+
+    def set_values(self, H, S):
+        mem = L.MEM_DEVICE if _is_device(H) or _is_device(S) else L.MEM_HOST
+        if mem == L.MEM_HOST:
+            H = None if H is None else np.ascontiguousarray(H, dtype=np.float64)
+            S = None if S is None else np.ascontiguousarray(S, dtype=np.float64)
+        L.check(self.lib.gsc_pair_set_values(self.h, _vp(H), _vp(S), mem))
+
+    def values(self):
+        shape = (self.nnzb, self.block, self.block)
+        H = np.empty(shape)
+        S = np.empty(shape)
+        L.check(self.lib.gsc_pair_get_values(self.h, _vp(H), _vp(S), L.MEM_HOST))
+        return H, S
+
+    def close(self):
+        if self.h:
+            self.lib.gsc_pair_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class AsedGeometry:
+    """Keeps the host arrays of one geometry alive for the C struct."""
+
+    def __init__(self, system, positions=None):
+        p = system.params
+        self.pos = np.ascontiguousarray(system.positions if positions is None else positions, dtype=np.float64)
+        self.orb_atom = np.ascontiguousarray(system.orb_atom, dtype=np.int32)
+        self.eps = np.ascontiguousarray(system.eps, dtype=np.float64)
+        self.trans = np.ascontiguousarray(system.trans, dtype=np.float64)
+        self.ang = np.ascontiguousarray(system.ang, dtype=np.float64)
+        self.struct = L.AsedGeom(self.pos.shape[0], _ptr(self.pos), _ptr(self.orb_atom, C.c_int32),
+                                 _ptr(self.eps), _ptr(self.trans), _ptr(self.ang),
+                                 p.s0, p.r0, p.lam, p.kappa, p.theta)
+
+
+def pair_from_system(ctx: Context, system, scale: float = 0.0, positions=None):
+    """Pattern of ``system`` plus S, H built on the device by the ASED
+    kernels (eq. Hap-1).  Returns (pair, scale c)."""
+    pair = Pair(ctx, system.block, system.rowptr, system.colidx)
+    c = ased_build(ctx, pair, system, scale, positions)
+    return pair, c
+
+
+def ased_build(ctx: Context, pair: Pair, system, scale: float = 0.0, positions=None) -> float:
+    g = AsedGeometry(system, positions)
+    out = C.c_double()
+    L.check(ctx.lib.gsc_ased_build(ctx.h, C.byref(g.struct), scale, pair.h, C.byref(out)))
+    return out.value
+
+
+def ased_vjp(ctx: Context, pair: Pair, system, scale: float, dH, dS, positions=None) -> np.ndarray:
+    g = AsedGeometry(system, positions)
+    mem = L.MEM_DEVICE if _is_device(dH) else L.MEM_HOST
+    if mem == L.MEM_HOST:
+        dH = np.ascontiguousarray(dH, dtype=np.float64)
+        dS = np.ascontiguousarray(dS, dtype=np.float64)
+    F = np.empty((g.pos.shape[0], 3))
+    L.check(ctx.lib.gsc_ased_vjp(ctx.h, C.byref(g.struct), scale, pair.h, _vp(dH), _vp(dS), mem, _ptr(F)))
+    return F
+
+
+def spmm(ctx: Context, pair: Pair, X, alpha_S):
+    """Y = alpha_S[c] * S X[:, c] - H X[:, c] for complex X (N, R)."""
+    alpha = _complex_view(np.broadcast_to(np.asarray(alpha_S, np.complex128), (X.shape[1],)).copy())
+    if _is_device(X):
+        import torch
+        Y = torch.empty_like(X)
+        L.check(ctx.lib.gsc_spmm(ctx.h, pair.h, X.shape[1], _ptr(alpha), _vp(X), _vp(Y), L.MEM_DEVICE))
+        return Y
+    Xv = np.ascontiguousarray(X, dtype=np.complex128)
+    Y = np.empty_like(Xv)
+    L.check(ctx.lib.gsc_spmm(ctx.h, pair.h, Xv.shape[1], _ptr(alpha), _vp(Xv.view(np.float64)),
+                             _vp(Y.view(np.float64)), L.MEM_HOST))
+    return Y
+
+
+def make_opts(tol=1e-10, max_iter=5000, inner_tol=0.0, inner_max_iter=200, precision="fp64",
+              carry="full", seed_index=-1, fuse_steps=0, rhs_tile=0, recheck=False) -> L.Opts:
+    o = L.Opts()
+    L.load().gsc_opts_default(C.byref(o))
+    o.tol, o.max_iter, o.inner_tol, o.inner_max_iter = tol, max_iter, inner_tol, inner_max_iter
+    o.precision = {"fp64": L.FP64, "mixed": L.MIXED}[precision]
+    o.carry = {"full": L.CARRY_FULL, "projected": L.CARRY_PROJECTED}[carry]
+    o.seed_index, o.fuse_steps, o.rhs_tile, o.recheck = seed_index, fuse_steps, rhs_tile, int(recheck)
+    return o
+
+
+@dataclass
+class SolveResult:
+    status: int
+    G_cols: object            # (K, R, N) complex or None
+    G_proj: object            # (K, R, P) complex or None
+    res: np.ndarray           # (K, R) recursive residual estimates
+    res_true: np.ndarray | None
+    converged: np.ndarray
+    outer_iters: int
+    inner_iters: int
+    switches: int
+    restarts: int
+    shift_rhs_iters: int
+    seconds: float
+
+
+def _stats(K, R, recheck):
+    res = np.zeros((K, R))
+    conv = np.zeros((K, R), np.uint8)
+    rt = np.zeros((K, R)) if recheck else None
+    st = L.Stats()
+    st.res_recursive = _ptr(res)
+    st.converged = _ptr(conv, C.c_ubyte)
+    st.res_true = _ptr(rt) if rt is not None else None
+    return st, res, conv, rt
+
+
+def solve(ctx: Context, pair: Pair, z, rhs=None, B=None, out: str = "host", want_cols: bool = True,
+          proj=None, **opt) -> SolveResult:
+    """(z_k S - H) x_k = b_r for all shifts and right-hand sides.
+
+    ``rhs``: orbital indices of unit right-hand sides; ``B``: dense (R, N)
+    complex right-hand sides instead.  ``proj``: (R, P) row indices whose
+    G values are returned.  ``out``: "host" (numpy) or "device" (torch)."""
+    z = np.ascontiguousarray(z, dtype=np.complex128)
+    K = z.shape[0]
+    opts = make_opts(**opt)
+    rhs_a = None if rhs is None else np.ascontiguousarray(rhs, dtype=np.int64)
+    R = len(rhs_a) if rhs_a is not None else B.shape[0]
+    N = pair.n
+    mem = L.MEM_DEVICE if out == "device" else L.MEM_HOST
+    carry_full = opts.carry == L.CARRY_FULL
+    Gc = Gp = None
+    Bv = None
+    if B is not None:
+        if mem == L.MEM_DEVICE:
+            import torch
+            Bv = torch.as_tensor(np.ascontiguousarray(B, np.complex128)).to(f"cuda:{ctx.device}")
+        else:
+            Bv = _complex_view(B)
+    P = 0
+    pidx = None
+    if proj is not None:
+        pidx = np.ascontiguousarray(proj, dtype=np.int64)
+        P = pidx.shape[1]
+    if mem == L.MEM_DEVICE:
+        import torch
+        dev = f"cuda:{ctx.device}"
+        if want_cols and carry_full:
+            Gc = torch.empty((K, R, N), dtype=torch.complex128, device=dev)
+        if P:
+            Gp = torch.empty((K, R, P), dtype=torch.complex128, device=dev)
+    else:
+        if want_cols and carry_full:
+            Gc = np.empty((K, R, N), np.complex128)
+        if P:
+            Gp = np.empty((K, R, P), np.complex128)
+    st, res, conv, rt = _stats(K, R, opts.recheck)
+
+    def vp(a):
+        if a is None:
+            return None
+        if isinstance(a, np.ndarray):
+            return _vp(a.view(np.float64) if a.dtype == np.complex128 else a)
+        return _vp(a)
+
+    status = ctx.lib.gsc_solve(ctx.h, pair.h, K, _ptr(_complex_view(z)), R,
+                               _ptr(rhs_a, C.c_int64) if rhs_a is not None else None,
+                               vp(Bv), C.byref(opts), vp(Gc), P,
+                               _ptr(pidx, C.c_int64) if pidx is not None else None, vp(Gp), mem,
+                               C.byref(st))
+    L.check(status)
+    return SolveResult(status, Gc, Gp, res, rt, conv.astype(bool), st.outer_iters, st.inner_iters,
+                       st.switches, st.restarts, st.shift_rhs_iters, st.seconds)
+
+
+def mulliken_band(ctx: Context, pair: Pair, z, w, orb, **opt):
+    """Per-orbital Mulliken charge q, band-energy contribution e and their
+    sum (Sec. 2.2).  Returns (q, e, e_band, stats dict)."""
+    z = np.ascontiguousarray(z, dtype=np.complex128)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    orb = np.ascontiguousarray(orb, dtype=np.int64)
+    K, R = z.shape[0], orb.shape[0]
+    opts = make_opts(**opt)
+    q = np.empty(R)
+    e = np.empty(R)
+    eb = C.c_double()
+    st, res, conv, _ = _stats(K, R, False)
+    status = ctx.lib.gsc_mulliken_band(ctx.h, pair.h, K, _ptr(_complex_view(z)), _ptr(w), R,
+                                       _ptr(orb, C.c_int64), C.byref(opts), _vp(q), _vp(e),
+                                       C.byref(eb), L.MEM_HOST, C.byref(st))
+    L.check(status)
+    info = dict(status=status, res=res, converged=conv.astype(bool), outer_iters=st.outer_iters,
+                inner_iters=st.inner_iters, switches=st.switches, restarts=st.restarts,
+                shift_rhs_iters=st.shift_rhs_iters, seconds=st.seconds)
+    return q, e, eb.value, info

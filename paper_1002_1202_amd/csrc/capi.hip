@@ -1,0 +1,421 @@
+// C ABI of the gsc library: argument validation, error mapping and the
+// reductions to Mulliken charges and band energy (Sec. 2.2).
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "pair.h"
+#include "solver.h"
+#include "spmm.h"
+
+struct gsc_ctx { gsc::Ctx c; };
+struct gsc_pair { gsc::Pair p; };
+
+namespace gsc {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+template <typename F> gsc_status guarded(F &&f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error &e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return GSC_E_NOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return GSC_E_DEVICE;
+    }
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) GSC_HIP(hipSetDevice(dev));
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// q_a = -(2/pi) sum_k w_k Im sg_ka ; e_a = -(2/pi) sum_k w_k E_k Im sg_ka
+__global__ void k_mulliken(int K, int R, const c128 *sg, size_t ld_k, size_t ld_r, const c128 *z,
+                           const double *w, double *q, double *e) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    double aq = 0.0, ae = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double im = sg[static_cast<size_t>(k) * ld_k + static_cast<size_t>(r) * ld_r].im;
+        aq += w[k] * im;
+        ae += w[k] * z[k].re * im;
+    }
+    const double f = -2.0 / M_PI;
+    q[r] = f * aq;
+    e[r] = f * ae;
+}
+
+__global__ void k_sum(int n, const double *v, double *out) {
+    __shared__ double lds[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += v[i];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) lds[threadIdx.x] += lds[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = lds[0];
+}
+
+__global__ void k_pad_cols(int N, int R, int Rp, const c128 *in, c128 *out, int to_padded) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(N) * Rp) return;
+    const int64_t i = t / Rp;
+    const int c = static_cast<int>(t % Rp);
+    if (to_padded) out[t] = c < R ? in[i * R + c] : c128{0, 0};
+    else if (c < R) out[i * R + c] = in[t];
+}
+
+void validate_opts(const gsc_opts &o) {
+    GSC_REQUIRE(o.tol > 0 && std::isfinite(o.tol), "tol must be positive");
+    GSC_REQUIRE(o.max_iter > 0, "max_iter must be positive");
+    GSC_REQUIRE(o.inner_max_iter > 0, "inner_max_iter must be positive");
+    GSC_REQUIRE(o.precision == GSC_FP64 || o.precision == GSC_MIXED, "unknown precision");
+    GSC_REQUIRE(o.carry == GSC_CARRY_FULL || o.carry == GSC_CARRY_PROJECTED, "unknown carry mode");
+    GSC_REQUIRE(o.fuse_steps >= 0 && o.fuse_steps <= kMaxFuse, "fuse_steps must be in [0, 16]");
+}
+
+void validate_shifts(int nshift, const double *z, int seed_index) {
+    GSC_REQUIRE(nshift >= 1 && z != nullptr, "need at least one shift");
+    for (int k = 0; k < nshift; ++k) {
+        GSC_REQUIRE(std::isfinite(z[2 * k]) && std::isfinite(z[2 * k + 1]), "shifts must be finite");
+        GSC_REQUIRE(z[2 * k + 1] > 0.0, "every shift needs Im z > 0 (z S - H must be nonsingular)");
+    }
+    GSC_REQUIRE(seed_index < nshift, "seed_index out of range");
+}
+
+}  // namespace gsc
+
+using namespace gsc;
+
+extern "C" {
+
+void gsc_opts_default(gsc_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-10;
+    o->max_iter = 5000;
+    o->inner_tol = 0.0;
+    o->inner_max_iter = 200;
+    o->precision = GSC_FP64;
+    o->carry = GSC_CARRY_FULL;
+    o->seed_index = -1;
+    o->fuse_steps = 0;
+    o->rhs_tile = 0;
+    o->recheck = 0;
+}
+
+const char *gsc_last_error(void) { return g_last_error.c_str(); }
+const char *gsc_version(void) { return "gsc 0.1 (gfx950)"; }
+
+gsc_status gsc_create(gsc_ctx **out, int device, void *stream) {
+    return guarded([&] {
+        GSC_REQUIRE(out != nullptr, "out must not be NULL");
+        int n = 0;
+        GSC_HIP(hipGetDeviceCount(&n));
+        GSC_REQUIRE(device >= 0 && device < n, "device ordinal out of range");
+        auto c = std::make_unique<gsc_ctx>();
+        c->c.device = device;
+        c->c.stream = static_cast<hipStream_t>(stream);
+        DeviceGuard g(device);
+        hipDeviceProp_t prop;
+        GSC_HIP(hipGetDeviceProperties(&prop, device));
+        c->c.num_cu = prop.multiProcessorCount;
+        *out = c.release();
+        return GSC_OK;
+    });
+}
+
+gsc_status gsc_set_stream(gsc_ctx *ctx, void *stream) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+        ctx->c.stream = static_cast<hipStream_t>(stream);
+        return GSC_OK;
+    });
+}
+
+void gsc_destroy(gsc_ctx *ctx) { delete ctx; }
+
+gsc_status gsc_pair_create(gsc_ctx *ctx, int block, int64_t nbrows, const int64_t *rowptr,
+                           const int32_t *colidx, const double *Hval, const double *Sval, int mem,
+                           gsc_pair **out) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr && out != nullptr, "ctx/out must not be NULL");
+        DeviceGuard g(ctx->c.device);
+        auto p = std::make_unique<gsc_pair>();
+        p->p.ctx = &ctx->c;
+        validate_and_upload(p->p, block, nbrows, rowptr, colidx);
+        if (Hval || Sval) set_values(p->p, Hval, Sval, mem);
+        *out = p.release();
+        return GSC_OK;
+    });
+}
+
+gsc_status gsc_pair_set_values(gsc_pair *pair, const double *Hval, const double *Sval, int mem) {
+    return guarded([&] {
+        GSC_REQUIRE(pair != nullptr, "pair must not be NULL");
+        DeviceGuard g(pair->p.ctx->device);
+        set_values(pair->p, Hval, Sval, mem);
+        return GSC_OK;
+    });
+}
+
+gsc_status gsc_pair_get_values(const gsc_pair *pair, double *Hval, double *Sval, int mem) {
+    return guarded([&] {
+        GSC_REQUIRE(pair != nullptr, "pair must not be NULL");
+        const Pair &p = pair->p;
+        DeviceGuard g(p.ctx->device);
+        const size_t nv = static_cast<size_t>(p.nnzb) * p.B * p.B;
+        const hipMemcpyKind kind = mem == GSC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        if (Hval) GSC_HIP(hipMemcpyAsync(Hval, p.H.get(), nv * 8, kind, p.ctx->stream));
+        if (Sval) GSC_HIP(hipMemcpyAsync(Sval, p.S.get(), nv * 8, kind, p.ctx->stream));
+        GSC_HIP(hipStreamSynchronize(p.ctx->stream));
+        return GSC_OK;
+    });
+}
+
+gsc_status gsc_pair_info(const gsc_pair *pair, int64_t *n, int64_t *nnzb, int *block) {
+    return guarded([&] {
+        GSC_REQUIRE(pair != nullptr, "pair must not be NULL");
+        if (n) *n = pair->p.n;
+        if (nnzb) *nnzb = pair->p.nnzb;
+        if (block) *block = pair->p.B;
+        return GSC_OK;
+    });
+}
+
+void gsc_pair_destroy(gsc_pair *pair) {
+    if (!pair) return;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(pair->p.ctx->device);
+    delete pair;
+    if (prev >= 0) (void)hipSetDevice(prev);
+}
+
+gsc_status gsc_ased_build(gsc_ctx *ctx, const gsc_ased_geom *geom, double scale, gsc_pair *pair,
+                          double *scale_out) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr && pair != nullptr, "ctx/pair must not be NULL");
+        DeviceGuard g(ctx->c.device);
+        const double c = ased_build(pair->p, geom, scale);
+        if (!(std::isfinite(c) && c > 0)) throw Error(GSC_E_NAN, "ASED scale is not finite");
+        if (scale_out) *scale_out = c;
+        return GSC_OK;
+    });
+}
+
+gsc_status gsc_ased_vjp(gsc_ctx *ctx, const gsc_ased_geom *geom, double scale, const gsc_pair *pair,
+                        const double *dHval, const double *dSval, int mem, double *forces) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr && pair != nullptr, "ctx/pair must not be NULL");
+        DeviceGuard g(ctx->c.device);
+        ased_vjp(pair->p, geom, scale, dHval, dSval, mem, forces);
+        return GSC_OK;
+    });
+}
+
+gsc_status gsc_spmm(gsc_ctx *ctx, const gsc_pair *pair, int nrhs, const double *alpha_S, const double *X,
+                    double *Y, int mem) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr && pair != nullptr, "ctx/pair must not be NULL");
+        GSC_REQUIRE(nrhs > 0 && alpha_S && X && Y, "bad spmm arguments");
+        DeviceGuard g(ctx->c.device);
+        const Pair &p = pair->p;
+        hipStream_t st = ctx->c.stream;
+        const int N = static_cast<int>(p.n);
+        const int Rp = (nrhs + 63) / 64 * 64;
+        DevBuf<c128> xin, xp(static_cast<size_t>(N) * Rp), yp(static_cast<size_t>(N) * Rp), yout;
+        const c128 *src = reinterpret_cast<const c128 *>(X);
+        if (mem != GSC_MEM_DEVICE) {
+            xin.alloc(static_cast<size_t>(N) * nrhs);
+            GSC_HIP(hipMemcpyAsync(xin.get(), X, xin.n * sizeof(c128), hipMemcpyHostToDevice, st));
+            src = xin.get();
+        }
+        const int64_t tot = static_cast<int64_t>(N) * Rp;
+        k_pad_cols<<<div_up(tot, 256), 256, 0, st>>>(N, nrhs, Rp, src, xp.get(), 1);
+        std::vector<c128> za(Rp, c128{0, 0});
+        std::vector<int> iota(Rp);
+        for (int c = 0; c < Rp; ++c) iota[c] = c;
+        for (int c = 0; c < nrhs; ++c) za[c] = c128{alpha_S[2 * c], alpha_S[2 * c + 1]};
+        DevBuf<c128> dz(Rp);
+        DevBuf<int> dseed(Rp);
+        GSC_HIP(hipMemcpyAsync(dz.get(), za.data(), Rp * sizeof(c128), hipMemcpyHostToDevice, st));
+        GSC_HIP(hipMemcpyAsync(dseed.get(), iota.data(), Rp * sizeof(int), hipMemcpyHostToDevice, st));
+        TileDims td{};
+        td.N = N; td.nb = static_cast<int>(p.nb); td.B = p.B; td.Rp = Rp;
+        td.Gs = std::max(8, std::min<int>((2048 / (Rp / 64) + 7) / 8 * 8, (td.nb + 7) / 8 * 8));
+        td.Lb = div_up(td.nb, td.Gs);
+        DevBuf<c128> part(static_cast<size_t>(td.Gs) * Rp);
+        launch_spmm_seed<double>(st, p, td, p.S.get(), p.H.get(), xp.get(), yp.get(), dz.get(), dseed.get(),
+                                 nullptr, part.get());
+        c128 *dst = reinterpret_cast<c128 *>(Y);
+        if (mem != GSC_MEM_DEVICE) {
+            yout.alloc(static_cast<size_t>(N) * nrhs);
+            dst = yout.get();
+        }
+        k_pad_cols<<<div_up(tot, 256), 256, 0, st>>>(N, nrhs, Rp, yp.get(), dst, 0);
+        GSC_HIP(hipGetLastError());
+        if (mem != GSC_MEM_DEVICE)
+            GSC_HIP(hipMemcpyAsync(Y, yout.get(), yout.n * sizeof(c128), hipMemcpyDeviceToHost, st));
+        GSC_HIP(hipStreamSynchronize(st));
+        return GSC_OK;
+    });
+}
+
+gsc_status gsc_solve(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const double *z, int nrhs,
+                     const int64_t *rhs_idx, const double *B_dense, const gsc_opts *opts, double *G_cols,
+                     int nproj, const int64_t *proj_idx, double *G_proj, int out_mem, gsc_stats *stats) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr && pair != nullptr, "ctx/pair must not be NULL");
+        gsc_opts o;
+        gsc_opts_default(&o);
+        if (opts) o = *opts;
+        validate_opts(o);
+        validate_shifts(nshift, z, o.seed_index);
+        const Pair &p = pair->p;
+        GSC_REQUIRE(nrhs >= 1, "need at least one right-hand side");
+        GSC_REQUIRE(rhs_idx != nullptr || B_dense != nullptr, "rhs_idx or B_dense is required");
+        if (rhs_idx)
+            for (int r = 0; r < nrhs; ++r) GSC_REQUIRE(rhs_idx[r] >= 0 && rhs_idx[r] < p.n, "rhs index out of range");
+        GSC_REQUIRE(nproj >= 0, "nproj must be >= 0");
+        if (nproj > 0) {
+            GSC_REQUIRE(proj_idx != nullptr && G_proj != nullptr, "proj_idx and G_proj are required when nproj > 0");
+            for (int64_t t = 0; t < static_cast<int64_t>(nrhs) * nproj; ++t)
+                GSC_REQUIRE(proj_idx[t] >= 0 && proj_idx[t] < p.n, "projection index out of range");
+        }
+        if (o.carry == GSC_CARRY_PROJECTED) {
+            GSC_REQUIRE(G_cols == nullptr, "G_cols needs the full carry");
+            GSC_REQUIRE(nproj > 0, "the projected carry needs projections");
+            GSC_REQUIRE(nproj <= 1024, "at most 1024 projections per rhs");
+        }
+        DeviceGuard g(ctx->c.device);
+        SolveRequest req;
+        req.pair = &p;
+        req.K = nshift;
+        req.z = z;
+        req.R = nrhs;
+        req.rhs_idx = rhs_idx;
+        req.B_dense = B_dense;
+        req.opts = o;
+        req.G_cols = G_cols;
+        req.out_mem = out_mem;
+        req.stats = stats;
+        ProjSpec ps;
+        DevBuf<c128> pout;
+        if (o.carry == GSC_CARRY_FULL) {
+            req.nproj = nproj;
+            req.proj_idx = proj_idx;
+            req.G_proj = G_proj;
+        } else {
+            ps.M = nproj;
+            ps.srow = false;
+            ps.idx.resize(static_cast<size_t>(nrhs) * nproj);
+            for (size_t t = 0; t < ps.idx.size(); ++t) ps.idx[t] = static_cast<int32_t>(proj_idx[t]);
+            req.proj = &ps;
+            if (out_mem == GSC_MEM_DEVICE) {
+                req.proj_out = reinterpret_cast<c128 *>(G_proj);
+            } else {
+                pout.alloc(static_cast<size_t>(nshift) * nrhs * nproj);
+                req.proj_out = pout.get();
+            }
+        }
+        const gsc_status s = run_solve(ctx->c, req);
+        if (pout.get()) {
+            GSC_HIP(hipMemcpyAsync(G_proj, pout.get(), pout.n * sizeof(c128), hipMemcpyDeviceToHost, ctx->c.stream));
+        }
+        GSC_HIP(hipStreamSynchronize(ctx->c.stream));
+        return s;
+    });
+}
+
+gsc_status gsc_mulliken_band(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const double *z, const double *w,
+                             int norb, const int64_t *orb_idx, const gsc_opts *opts, double *q_orb,
+                             double *e_orb, double *e_band, int out_mem, gsc_stats *stats) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr && pair != nullptr, "ctx/pair must not be NULL");
+        gsc_opts o;
+        gsc_opts_default(&o);
+        if (opts) o = *opts;
+        validate_opts(o);
+        validate_shifts(nshift, z, o.seed_index);
+        GSC_REQUIRE(w != nullptr, "weights must not be NULL");
+        GSC_REQUIRE(norb >= 1 && orb_idx != nullptr, "need at least one orbital");
+        const Pair &p = pair->p;
+        for (int r = 0; r < norb; ++r) GSC_REQUIRE(orb_idx[r] >= 0 && orb_idx[r] < p.n, "orbital index out of range");
+        DeviceGuard g(ctx->c.device);
+        hipStream_t st = ctx->c.stream;
+        SolveRequest req;
+        req.pair = &p;
+        req.K = nshift;
+        req.z = z;
+        req.R = norb;
+        req.rhs_idx = orb_idx;
+        req.opts = o;
+        req.out_mem = GSC_MEM_DEVICE;
+        req.stats = stats;
+        DevBuf<c128> sg(static_cast<size_t>(nshift) * norb);
+        ProjSpec ps;
+        if (o.carry == GSC_CARRY_FULL) {
+            req.sg_diag = sg.get();
+        } else {
+            ps.M = 0;
+            ps.srow = true;
+            req.proj = &ps;
+            req.proj_out = sg.get();
+        }
+        const gsc_status s = run_solve(ctx->c, req);
+        DevBuf<c128> dz(nshift);
+        DevBuf<double> dw(nshift), dq(norb), de(norb), deb(1);
+        GSC_HIP(hipMemcpyAsync(dz.get(), z, nshift * sizeof(c128), hipMemcpyHostToDevice, st));
+        GSC_HIP(hipMemcpyAsync(dw.get(), w, nshift * sizeof(double), hipMemcpyHostToDevice, st));
+        k_mulliken<<<div_up(norb, 256), 256, 0, st>>>(nshift, norb, sg.get(), norb, 1, dz.get(), dw.get(), dq.get(),
+                                                      de.get());
+        k_sum<<<1, 256, 0, st>>>(norb, de.get(), deb.get());
+        GSC_HIP(hipGetLastError());
+        const hipMemcpyKind kind = out_mem == GSC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        if (q_orb) GSC_HIP(hipMemcpyAsync(q_orb, dq.get(), norb * 8, kind, st));
+        if (e_orb) GSC_HIP(hipMemcpyAsync(e_orb, de.get(), norb * 8, kind, st));
+        double eb = 0.0;
+        GSC_HIP(hipMemcpyAsync(&eb, deb.get(), 8, hipMemcpyDeviceToHost, st));
+        GSC_HIP(hipStreamSynchronize(st));
+        if (e_band) *e_band = eb;
+        return s;
+    });
+}
+
+gsc_status gsc_band_energy_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const double *z, const double *w,
+                               double grad_E, const gsc_opts *opts, double *dHval, double *dSval, double *e_band,
+                               int mem, gsc_stats *stats) {
+    (void)ctx; (void)pair; (void)nshift; (void)z; (void)w; (void)grad_E; (void)opts;
+    (void)dHval; (void)dSval; (void)e_band; (void)mem; (void)stats;
+    set_last_error("gsc_band_energy_vjp: not built yet");
+    return GSC_E_UNSUPPORTED;
+}
+
+gsc_status gsc_solve_batched(gsc_ctx *ctx, int nsys, const gsc_problem *problems, const gsc_opts *opts) {
+    (void)ctx; (void)nsys; (void)problems; (void)opts;
+    set_last_error("gsc_solve_batched: not built yet");
+    return GSC_E_UNSUPPORTED;
+}
+
+}  // extern "C"

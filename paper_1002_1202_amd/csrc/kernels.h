@@ -1,0 +1,66 @@
+// Device kernels of the generalized shifted COCG solve (Sec. 3.3).
+//
+// Layouts (one device tile of Rp right-hand sides; Rp is a multiple of 64):
+//   seed vectors   v[i*Rp + c]            complex, i < N, c < Rp
+//   ring of r'     ring[t][i*Rp + c]      t < m   (r'_n lives in slot n % m)
+//   shifted        X[k*ldk + c*N + i]     complex (x^k and p^k, full carry)
+//   (k, c) scalars s[k*Rp + c]            FP64
+//   column scalars col[c]                 FP64
+// A wave of 64 lanes covers 64 consecutive columns; rows are split over the
+// grid's y dimension (row groups), remapped so that each XCD works on one
+// contiguous range of rows (neighbour reuse stays inside one L2).
+#pragma once
+
+#include "common.h"
+
+namespace gsc {
+
+constexpr int kMaxFuse = 16;          // largest m of the fused shift update
+constexpr int kFrozenNever = 0x7fffffff;
+
+enum : int { FLAG_BREAKDOWN = 1, FLAG_NOT_SPD = 2, FLAG_NAN = 4, FLAG_INNER = 8 };
+
+// Column (right-hand side) state of one tile, all FP64.
+struct ColState {
+    c128 *rho, *alpha, *alpha_prev, *beta_prev, *swc, *swcm;
+    double *bnorm, *rnorm2, *rr, *rr_stop, *cg_a, *cg_b;
+    int *seed, *done, *inner_done, *cg_first, *sw, *applied, *flags, *zres;
+    int *inner_count;
+    long long *shift_iters;
+    int *iters;
+};
+
+// (shift, column) state.
+struct ShiftState {
+    const c128 *z;            // [K]
+    c128 *pi, *pi_prev, *pi_next;
+    c128 *omega;              // collinear-restart weights (projected carry)
+    double *res;              // recursive residual estimate at freeze / exit
+    int *last;                // last active step (kFrozenNever while active)
+    c128 *ra, *rb, *rc;       // [m][K][Rp] shift-update coefficients
+};
+
+struct TileDims {
+    int N, nb, B, K, R, Rp, m;
+    int G;                    // row groups of the vector kernels (multiple of 8)
+    int Lr;                   // rows per group (vector kernels)
+    int Gs;                   // row groups of the SpMM kernels (multiple of 8)
+    int Lb;                   // block rows per SpMM group
+};
+
+// XCD-aware remap of the linear block id: blocks l = x + gx*y are dispatched
+// round-robin over the 8 XCDs; give each XCD a contiguous slice of the
+// logical (x, y) space.
+__device__ inline void xcd_remap(int &cx, int &gy) {
+    const int gx = gridDim.x;
+    const int total = gx * gridDim.y;
+    const int l = blockIdx.x + gx * blockIdx.y;
+    const int per = total >> 3;
+    const int lp = (l & 7) * per + (l >> 3);
+    cx = lp % gx;
+    gy = lp / gx;
+}
+
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+}  // namespace gsc

@@ -1,0 +1,46 @@
+#pragma once
+#include "kernels.h"
+
+namespace gsc {
+
+struct Status {
+    int active_cols;       // columns with at least one unconverged shift
+    int inner_pending;     // columns whose inner S-solve has not converged
+    int switched;          // columns that switched seed (or restarted) this iteration
+    int flags;             // OR of FLAG_* over columns
+};
+
+// Projections carried by the projected mode: M unit vectors c_m = e_i per
+// column (idx[c*M + m] = i, for G_ij), optionally followed by c = S e_a with
+// a the column's unit right-hand side (for (S G)_aa, the Mulliken charge).
+struct ProjSpec {
+    int M = 0;                          // unit projections e_i per column
+    bool srow = false;                  // also carry c = S e_a, a = rhs[c] (last slot)
+    std::vector<int32_t> idx;           // [R][M]
+};
+
+struct SolveRequest {
+    const Pair *pair = nullptr;
+    int K = 0;
+    const double *z = nullptr;          // host, 2K
+    int R = 0;
+    const int64_t *rhs_idx = nullptr;   // host
+    const double *B_dense = nullptr;    // [R][N] complex, per out_mem
+    gsc_opts opts{};
+    // full carry outputs
+    double *G_cols = nullptr;           // [K][R][N] complex
+    int nproj = 0;
+    const int64_t *proj_idx = nullptr;  // host [R][nproj]
+    double *G_proj = nullptr;           // [K][R][nproj] complex
+    int out_mem = GSC_MEM_HOST;
+    // projected carry: projection spec and output [K][R][M] complex (device)
+    const ProjSpec *proj = nullptr;
+    c128 *proj_out = nullptr;           // device [K][R][M]
+    // (S G)_aa for unit rhs: device [K][R] complex (full carry Mulliken path)
+    c128 *sg_diag = nullptr;
+    gsc_stats *stats = nullptr;
+};
+
+gsc_status run_solve(Ctx &ctx, SolveRequest &req);
+
+}  // namespace gsc

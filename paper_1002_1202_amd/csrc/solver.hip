@@ -1,0 +1,1256 @@
+// Generalized shifted COCG (Sec. 3.3) for one tile of right-hand sides.
+//
+// Per outer iteration n (every kernel masks finished columns):
+//   spmm_seed   q = A_s p = z_s S p - H p,  partial p^T q          (eq. CGp:r)
+//   ctrl        alpha = rho / p^T q; per shift pi_{n+1} (eq. Shift:pi with the
+//               derived sign) and the update coefficients 1/pi_n, beta^k, alpha^k
+//   shift upd.  p^k <- r'_n/pi_n + beta^k p^k,  x^k <- x^k + alpha^k p^k
+//               (full carry: deferred and applied m steps per pass; projected
+//               carry: on the projections c^T x^k, c^T p^k)
+//   update_r    r <- r - alpha q                                    (eq. CGp:r)
+//   inner CG    r' = S^{-1} r (Sec. 3.3: S is positive definite and close to I)
+//   post        rho' = r'^T r, beta = rho'/rho; pi shift; ||r||/(|pi| ||b||)
+//               freezes converged shifts (eq. Collinear); seed switching
+//   p_update    p <- r' + beta p                                    (eq. CGp:p)
+// All scalar recurrences, dots and reductions are FP64; vectors and products
+// are complex<T> (T = double, or float in the mixed mode).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "solver.h"
+#include "spmm.h"
+
+namespace gsc {
+
+// ------------------------------------------------------------------ helpers
+template <typename V>
+__device__ inline V block_sum(V v, V *lds) {
+    lds[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) lds[threadIdx.x] = lds[threadIdx.x] + lds[threadIdx.x + s];
+        __syncthreads();
+    }
+    V r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+// Row range of the vector kernels: group g covers rows [g*Lr, (g+1)*Lr).
+#define ELEM_LOOP_BEGIN                                     \
+    int cx, g;                                              \
+    xcd_remap(cx, g);                                       \
+    const int lane = threadIdx.x & 63;                      \
+    const int wv = wave_id();                               \
+    const int col = cx * 64 + lane;                         \
+    const int i0 = g * Lr;                                  \
+    const int i1 = min(N, i0 + Lr);
+
+template <typename V>
+__device__ inline void wave_partial_store(V v, V *partial, int g, int Rp, int col) {
+    __shared__ V red[kWavesPerBlock][64];
+    const int lane = threadIdx.x & 63;
+    red[threadIdx.x >> 6][lane] = v;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        V s = red[0][lane];
+#pragma unroll
+        for (int k = 1; k < kWavesPerBlock; ++k) s = s + red[k][lane];
+        partial[static_cast<size_t>(g) * Rp + col] = s;
+    }
+}
+
+// ------------------------------------------------------------------ init
+__global__ void k_init_cols(int R, int Rp, int seed0, ColState cs) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= Rp) return;
+    cs.seed[c] = seed0;
+    cs.done[c] = c >= R ? 1 : 0;
+    cs.alpha_prev[c] = {1.0, 0.0};
+    cs.beta_prev[c] = {0.0, 0.0};
+    cs.alpha[c] = {0.0, 0.0};
+    cs.rho[c] = {0.0, 0.0};
+    cs.flags[c] = 0;
+    cs.applied[c] = 0;
+    cs.sw[c] = 0;
+    cs.shift_iters[c] = 0;
+    cs.iters[c] = 0;
+    cs.zres[c] = 0;
+    cs.inner_done[c] = 1;
+    cs.inner_count[c] = 0;
+}
+
+__global__ void k_init_shifts(int K, int R, int Rp, ShiftState ss) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(K) * Rp) return;
+    const int c = static_cast<int>(t % Rp);
+    ss.pi[t] = {1.0, 0.0};
+    ss.pi_prev[t] = {1.0, 0.0};
+    ss.pi_next[t] = {1.0, 0.0};
+    ss.omega[t] = {1.0, 0.0};
+    ss.res[t] = 0.0;
+    ss.last[t] = c < R ? kFrozenNever : -1;
+}
+
+// r = b; res = d = r; partial ||r||^2.  Unit rhs (rhs != null) or dense B[c][i].
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init_rhs(int N, int Rp, int Lr, int R, const int64_t *rhs,
+                                                     const c128 *Bd, cpx<T> *r, cpx<T> *res, cpx<T> *d,
+                                                     double *partial) {
+    ELEM_LOOP_BEGIN
+    double acc = 0.0;
+    const int64_t j = (rhs != nullptr && col < R) ? rhs[col] : -1;
+    for (int i = i0 + wv; i < i1; i += kWavesPerBlock) {
+        cpx<T> v{0, 0};
+        if (col < R) {
+            if (rhs != nullptr) v = (i == j) ? cpx<T>{1, 0} : cpx<T>{0, 0};
+            else v = ccast<T>(Bd[static_cast<size_t>(col) * N + i]);
+        }
+        const size_t e = static_cast<size_t>(i) * Rp + col;
+        r[e] = v;
+        res[e] = v;
+        d[e] = v;
+        acc += static_cast<double>(v.re) * v.re + static_cast<double>(v.im) * v.im;
+    }
+    wave_partial_store(acc, partial, g, Rp, col);
+}
+
+template <typename T>
+__global__ void k_zero_shifted(int K, int R, int N, size_t ldk, cpx<T> *X) {
+    const int64_t per = static_cast<int64_t>(R) * N;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= per * K) return;
+    const int64_t k = t / per, o = t % per;
+    X[k * ldk + o] = {0, 0};
+}
+
+// ------------------------------------------------------------------ column kernels
+// ||r||^2 reduction; prepares the inner solve of S r' = r.
+__global__ __launch_bounds__(kBlock) void k_col_rnorm(int Rp, int G, const double *partial, int init,
+                                                      double inner_tol, ColState cs) {
+    __shared__ double lds[kBlock];
+    const int c = blockIdx.x;
+    double v = 0.0;
+    for (int g = threadIdx.x; g < G; g += kBlock) v += partial[static_cast<size_t>(g) * Rp + c];
+    const double rn2 = block_sum(v, lds);
+    if (threadIdx.x != 0) return;
+    if (cs.done[c]) { cs.inner_done[c] = 1; return; }
+    cs.rnorm2[c] = rn2;
+    if (init) {
+        cs.bnorm[c] = sqrt(rn2);
+        if (rn2 == 0.0) cs.done[c] = 1;      // b = 0: x = 0 for every shift
+    }
+    if (!isfinite(rn2)) { cs.flags[c] |= FLAG_NAN; cs.done[c] = 1; }
+    cs.rr[c] = rn2;
+    cs.rr_stop[c] = inner_tol * inner_tol * rn2;
+    cs.zres[c] = rn2 == 0.0 ? 1 : 0;
+    cs.inner_done[c] = (rn2 == 0.0 || cs.done[c]) ? 1 : 0;
+    cs.cg_first[c] = 1;
+    cs.inner_count[c] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_a(int Rp, int G, const double *partial, ColState cs) {
+    __shared__ double lds[kBlock];
+    const int c = blockIdx.x;
+    if (cs.inner_done[c]) return;
+    double v = 0.0;
+    for (int g = threadIdx.x; g < G; g += kBlock) v += partial[static_cast<size_t>(g) * Rp + c];
+    const double dw = block_sum(v, lds);
+    if (threadIdx.x != 0) return;
+    if (!(dw > 0.0)) {
+        cs.flags[c] |= isfinite(dw) ? FLAG_NOT_SPD : FLAG_NAN;
+        cs.inner_done[c] = 1;
+        cs.done[c] = 1;
+        cs.cg_a[c] = 0.0;
+        return;
+    }
+    cs.cg_a[c] = cs.rr[c] / dw;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_b(int Rp, int G, const double *partial, int inner_max,
+                                                 ColState cs) {
+    __shared__ double lds[kBlock];
+    const int c = blockIdx.x;
+    if (cs.inner_done[c]) return;
+    double v = 0.0;
+    for (int g = threadIdx.x; g < G; g += kBlock) v += partial[static_cast<size_t>(g) * Rp + c];
+    const double rr_new = block_sum(v, lds);
+    if (threadIdx.x != 0) return;
+    const double rr = cs.rr[c];
+    cs.cg_b[c] = rr_new / rr;
+    cs.rr[c] = rr_new;
+    cs.cg_first[c] = 0;
+    const int cnt = ++cs.inner_count[c];
+    if (!isfinite(rr_new)) {
+        cs.flags[c] |= FLAG_NAN;
+        cs.done[c] = 1;
+        cs.inner_done[c] = 1;
+    } else if (rr_new <= cs.rr_stop[c]) {
+        cs.inner_done[c] = 1;
+    } else if (cnt >= inner_max) {
+        cs.flags[c] |= FLAG_INNER;
+        cs.inner_done[c] = 1;
+    }
+}
+
+// alpha = rho / (p^T A_s p) and the shift coefficients of step n (slot).
+__global__ __launch_bounds__(kBlock) void k_ctrl(int K, int Rp, int G, int slot, const c128 *partial,
+                                                 ColState cs, ShiftState ss) {
+    __shared__ c128 lds[kBlock];
+    __shared__ c128 s_alpha, s_tail, s_zs;
+    __shared__ int s_ok;
+    __shared__ long long s_cnt[kBlock];
+    const int c = blockIdx.x;
+    if (cs.done[c]) return;
+    c128 v{0, 0};
+    for (int g = threadIdx.x; g < G; g += kBlock) v = v + partial[static_cast<size_t>(g) * Rp + c];
+    const c128 mu = block_sum(v, lds);
+    if (threadIdx.x == 0) {
+        cs.sw[c] = 0;
+        const c128 rho = cs.rho[c];
+        const c128 alpha = cdiv(rho, mu);
+        int ok = 1;
+        if (!cfinite(mu) || !cfinite(alpha)) {
+            cs.flags[c] |= cfinite(mu) ? FLAG_BREAKDOWN : FLAG_NAN;
+            ok = 0;
+        } else if (cabs(mu) == 0.0 || cabs(alpha) == 0.0) {
+            cs.flags[c] |= FLAG_BREAKDOWN;
+            ok = 0;
+        }
+        if (!ok) cs.done[c] = 1;
+        cs.alpha[c] = alpha;
+        s_alpha = alpha;
+        s_tail = cdiv(alpha * cs.beta_prev[c], cs.alpha_prev[c]);
+        s_zs = ss.z[cs.seed[c]];
+        s_ok = ok;
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    const c128 alpha = s_alpha, tail = s_tail, zs = s_zs;
+    const size_t KR = static_cast<size_t>(K) * Rp;
+    long long cnt = 0;
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+        const size_t idx = static_cast<size_t>(k) * Rp + c;
+        if (ss.last[idx] != kFrozenNever) continue;
+        ++cnt;
+        const c128 pi = ss.pi[idx], pim = ss.pi_prev[idx];
+        const c128 delta = ss.z[k] - zs;
+        const c128 lead = c128{1.0, 0.0} + alpha * delta;
+        const c128 pin = lead * pi + tail * (pi - pim);
+        ss.pi_next[idx] = pin;
+        const c128 q = cdiv(pim, pi);
+        ss.ra[slot * KR + idx] = cdiv(c128{1.0, 0.0}, pi);
+        ss.rb[slot * KR + idx] = (q * q) * cs.beta_prev[c];
+        ss.rc[slot * KR + idx] = ss.omega[idx] * cdiv(alpha * pi, pin);
+    }
+    s_cnt[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) s_cnt[threadIdx.x] += s_cnt[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cs.shift_iters[c] += s_cnt[0];
+        cs.iters[c] += 1;
+    }
+}
+
+// rho' = r'^T r; beta; pi shift; freeze; seed switch / collinear restart.
+__global__ __launch_bounds__(kBlock) void k_post(int K, int Rp, int G, int n, int full_carry,
+                                                 const c128 *partial, double tol, ColState cs,
+                                                 ShiftState ss, c128 *proj_h, int M) {
+    __shared__ c128 lds[kBlock];
+    __shared__ double s_res[kBlock];
+    __shared__ int s_k[kBlock];
+    __shared__ int s_cnt[kBlock];
+    __shared__ int s_sw;
+    __shared__ c128 s_c, s_cm;
+    const int c = blockIdx.x;
+    if (cs.done[c]) return;
+    c128 v{0, 0};
+    for (int g = threadIdx.x; g < G; g += kBlock) v = v + partial[static_cast<size_t>(g) * Rp + c];
+    const c128 rho_new = block_sum(v, lds);
+    const double rn = sqrt(cs.rnorm2[c]);
+    const double bn = cs.bnorm[c];
+    double best = -1.0;
+    int bestk = 0x7fffffff, cnt = 0;
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+        const size_t idx = static_cast<size_t>(k) * Rp + c;
+        if (ss.last[idx] != kFrozenNever) continue;
+        const c128 pin = ss.pi_next[idx];
+        ss.pi_prev[idx] = ss.pi[idx];
+        ss.pi[idx] = pin;
+        const double res = cabs(ss.omega[idx]) * rn / (cabs(pin) * bn);
+        ss.res[idx] = res;
+        if (!(res > tol)) {
+            ss.last[idx] = n;
+        } else {
+            ++cnt;
+            if (res > best) { best = res; bestk = k; }
+        }
+    }
+    s_res[threadIdx.x] = best;
+    s_k[threadIdx.x] = bestk;
+    s_cnt[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double r2 = s_res[threadIdx.x + s];
+            const int k2 = s_k[threadIdx.x + s];
+            if (r2 > s_res[threadIdx.x] || (r2 == s_res[threadIdx.x] && k2 < s_k[threadIdx.x])) {
+                s_res[threadIdx.x] = r2;
+                s_k[threadIdx.x] = k2;
+            }
+            s_cnt[threadIdx.x] += s_cnt[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const c128 rho = cs.rho[c];
+        const c128 beta = cdiv(rho_new, rho);
+        cs.alpha_prev[c] = cs.alpha[c];
+        cs.beta_prev[c] = beta;
+        cs.rho[c] = rho_new;
+        int sw = 0;
+        if (s_cnt[0] == 0) {
+            cs.done[c] = 1;
+        } else if (!cfinite(rho_new) || !cfinite(beta)) {
+            cs.flags[c] |= FLAG_NAN;
+            cs.done[c] = 1;
+        } else if (cabs(rho_new) == 0.0) {
+            cs.flags[c] |= FLAG_BREAKDOWN;
+            cs.done[c] = 1;
+        } else {
+            const int seed = cs.seed[c];
+            if (ss.last[static_cast<size_t>(seed) * Rp + c] != kFrozenNever) {
+                const int sn = s_k[0];
+                const size_t ix = static_cast<size_t>(sn) * Rp + c;
+                const c128 cc = ss.pi[ix], ccm = ss.pi_prev[ix];
+                if (full_carry) {
+                    // exact seed switch: rescale the seed quantities by pi of
+                    // the new seed; shifted iterates are invariant
+                    const c128 q = cdiv(ccm, cc);
+                    cs.rho[c] = cdiv(rho_new, cc * cc);
+                    cs.beta_prev[c] = (q * q) * beta;
+                    cs.alpha_prev[c] = cs.alpha[c] * q;
+                    sw = 1;
+                } else {
+                    // collinear restart on the current residual
+                    cs.alpha_prev[c] = {1.0, 0.0};
+                    cs.beta_prev[c] = {0.0, 0.0};
+                    sw = 2;
+                }
+                cs.seed[c] = sn;
+                cs.swc[c] = cc;
+                cs.swcm[c] = ccm;
+                s_c = cc;
+                s_cm = ccm;
+            }
+        }
+        cs.sw[c] = sw;
+        s_sw = cs.done[c] ? 0 : sw;
+    }
+    __syncthreads();
+    const int sw = s_sw;
+    if (sw == 1) {
+        const c128 cc = s_c, ccm = s_cm;
+        for (int k = threadIdx.x; k < K; k += kBlock) {
+            const size_t idx = static_cast<size_t>(k) * Rp + c;
+            ss.pi[idx] = cdiv(ss.pi[idx], cc);
+            ss.pi_prev[idx] = cdiv(ss.pi_prev[idx], ccm);
+        }
+    } else if (sw == 2) {
+        for (int k = threadIdx.x; k < K; k += kBlock) {
+            const size_t idx = static_cast<size_t>(k) * Rp + c;
+            if (ss.last[idx] == kFrozenNever) ss.omega[idx] = cdiv(ss.omega[idx], ss.pi[idx]);
+            ss.pi[idx] = {1.0, 0.0};
+            ss.pi_prev[idx] = {1.0, 0.0};
+            if (proj_h != nullptr)
+                for (int m = 0; m < M; ++m) proj_h[(static_cast<size_t>(k) * Rp + c) * M + m] = {0, 0};
+        }
+    }
+}
+
+__global__ void k_init_rho(int Rp, int G, const c128 *partial, ColState cs) {
+    __shared__ c128 lds[kBlock];
+    const int c = blockIdx.x;
+    c128 v{0, 0};
+    for (int g = threadIdx.x; g < G; g += kBlock) v = v + partial[static_cast<size_t>(g) * Rp + c];
+    const c128 rho = block_sum(v, lds);
+    if (threadIdx.x == 0 && !cs.done[c]) {
+        cs.rho[c] = rho;
+        if (!cfinite(rho)) { cs.flags[c] |= FLAG_NAN; cs.done[c] = 1; }
+        else if (cabs(rho) == 0.0) { cs.flags[c] |= FLAG_BREAKDOWN; cs.done[c] = 1; }
+    }
+}
+
+__global__ void k_status(int Rp, ColState cs, Status *st) {
+    __shared__ int a[kBlock], b[kBlock], s[kBlock], f[kBlock];
+    int na = 0, nb = 0, ns = 0, fl = 0;
+    for (int c = threadIdx.x; c < Rp; c += kBlock) {
+        const int done = cs.done[c];
+        na += !done;
+        nb += (!done && !cs.inner_done[c]);
+        ns += (!done && cs.sw[c] != 0);
+        fl |= cs.flags[c];
+    }
+    a[threadIdx.x] = na; b[threadIdx.x] = nb; s[threadIdx.x] = ns; f[threadIdx.x] = fl;
+    __syncthreads();
+    for (int k = kBlock / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) {
+            a[threadIdx.x] += a[threadIdx.x + k];
+            b[threadIdx.x] += b[threadIdx.x + k];
+            s[threadIdx.x] += s[threadIdx.x + k];
+            f[threadIdx.x] |= f[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        st->active_cols = a[0];
+        st->inner_pending = b[0];
+        st->switched = s[0];
+        st->flags = f[0];
+    }
+}
+
+// ------------------------------------------------------------------ vector kernels
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_r(int N, int Rp, int Lr, const int *done,
+                                                     const c128 *alpha, const cpx<T> *q, cpx<T> *r,
+                                                     cpx<T> *res, cpx<T> *d, double *partial) {
+    ELEM_LOOP_BEGIN
+    double acc = 0.0;
+    if (!done[col]) {
+        const cpx<T> a = ccast<T>(alpha[col]);
+        for (int i = i0 + wv; i < i1; i += kWavesPerBlock) {
+            const size_t e = static_cast<size_t>(i) * Rp + col;
+            const cpx<T> v = r[e] - a * q[e];
+            r[e] = v;
+            res[e] = v;
+            d[e] = v;
+            acc += static_cast<double>(v.re) * v.re + static_cast<double>(v.im) * v.im;
+        }
+    }
+    wave_partial_store(acc, partial, g, Rp, col);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update(int N, int Rp, int Lr, const int *inner_done,
+                                                      const int *first, const double *cg_a,
+                                                      const cpx<T> *d, const cpx<T> *w, cpx<T> *y,
+                                                      cpx<T> *res, double *partial) {
+    ELEM_LOOP_BEGIN
+    double acc = 0.0;
+    if (!inner_done[col]) {
+        const T a = static_cast<T>(cg_a[col]);
+        const bool f = first[col] != 0;
+        for (int i = i0 + wv; i < i1; i += kWavesPerBlock) {
+            const size_t e = static_cast<size_t>(i) * Rp + col;
+            const cpx<T> dv = d[e];
+            const cpx<T> yv = f ? a * dv : y[e] + a * dv;
+            y[e] = yv;
+            const cpx<T> rv = res[e] - a * w[e];
+            res[e] = rv;
+            acc += static_cast<double>(rv.re) * rv.re + static_cast<double>(rv.im) * rv.im;
+        }
+    }
+    wave_partial_store(acc, partial, g, Rp, col);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_dir(int N, int Rp, int Lr, const int *inner_done,
+                                                   const double *cg_b, const cpx<T> *res, cpx<T> *d) {
+    ELEM_LOOP_BEGIN
+    if (inner_done[col]) return;
+    const T b = static_cast<T>(cg_b[col]);
+    for (int i = i0 + wv; i < i1; i += kWavesPerBlock) {
+        const size_t e = static_cast<size_t>(i) * Rp + col;
+        d[e] = res[e] + b * d[e];
+    }
+}
+
+// partial r'^T r (unconjugated)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_rho_dot(int N, int Rp, int Lr, const int *done, const int *zres,
+                                                    const cpx<T> *rp, const cpx<T> *r, c128 *partial) {
+    ELEM_LOOP_BEGIN
+    c128 acc{0, 0};
+    if (!done[col] && !zres[col]) {
+        for (int i = i0 + wv; i < i1; i += kWavesPerBlock) {
+            const size_t e = static_cast<size_t>(i) * Rp + col;
+            acc = acc + ccast<double>(rp[e]) * ccast<double>(r[e]);
+        }
+    }
+    wave_partial_store(acc, partial, g, Rp, col);
+}
+
+// p <- r' + beta p (eq. CGp:p); at a seed switch p <- r'/c + beta p^{s'} with
+// r, r' rescaled by 1/c; at a collinear restart (or init) p <- r'.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_p_update(int N, int Rp, int Lr, int init, ColState cs,
+                                                     cpx<T> *rp, cpx<T> *r, cpx<T> *p, const cpx<T> *P,
+                                                     size_t ldk) {
+    ELEM_LOOP_BEGIN
+    if (cs.done[col]) return;
+    const int sw = init ? 2 : cs.sw[col];
+    const cpx<T> beta = ccast<T>(cs.beta_prev[col]);
+    if (sw == 1) {
+        const c128 cc = cs.swc[col];
+        const c128 inv = cdiv(c128{1.0, 0.0}, cc);
+        const cpx<T> ci = ccast<T>(inv);
+        const cpx<T> *Ps = P + static_cast<size_t>(cs.seed[col]) * ldk + static_cast<size_t>(col) * N;
+        for (int i = i0 + wv; i < i1; i += kWavesPerBlock) {
+            const size_t e = static_cast<size_t>(i) * Rp + col;
+            const cpx<T> v = ci * rp[e];
+            rp[e] = v;
+            r[e] = ci * r[e];
+            p[e] = v + beta * Ps[i];
+        }
+    } else if (sw == 2) {
+        for (int i = i0 + wv; i < i1; i += kWavesPerBlock) {
+            const size_t e = static_cast<size_t>(i) * Rp + col;
+            p[e] = rp[e];
+        }
+    } else {
+        for (int i = i0 + wv; i < i1; i += kWavesPerBlock) {
+            const size_t e = static_cast<size_t>(i) * Rp + col;
+            p[e] = rp[e] + beta * p[e];
+        }
+    }
+}
+
+__global__ void k_mark_applied(int Rp, int n1, ColState cs) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < Rp && cs.sw[c] == 1) cs.applied[c] = n1;
+}
+
+// ------------------------------------------------------------------ fused shift update
+// Applies the pending steps t in [max(n0, applied[c]), n1) of the shifted
+// recurrences to x^k, p^k of column c:  p <- a_t r'_t + b_t p;  x <- x + c_t p,
+// skipping steps after a shift froze.  r'_t stays in registers across all
+// shifts of the block; x^k, p^k are read and written once per pass.
+template <typename T, int M, int E>
+__global__ __launch_bounds__(kBlock) void k_flush(int N, int Rp, int K, int m, int n0, int n1, int only_sw,
+                                                  int kper, ColState cs, ShiftState ss,
+                                                  const cpx<T> *ring, size_t ring_ld, cpx<T> *X, size_t ldx,
+                                                  cpx<T> *P, size_t ldp) {
+    const int col = blockIdx.y;
+    if (only_sw && cs.sw[col] != 1) return;
+    const int tb = max(n0, cs.applied[col]);
+    const int cnt = n1 - tb;
+    if (cnt <= 0) return;
+    const int ibase = blockIdx.x * (kBlock * E) + threadIdx.x;
+    cpx<T> rr[M][E];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const int slot = (tb + j) % m;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = ibase + e * kBlock;
+            rr[j][e] = (j < cnt && i < N) ? ring[slot * ring_ld + static_cast<size_t>(i) * Rp + col]
+                                          : cpx<T>{0, 0};
+        }
+    }
+    const size_t KR = static_cast<size_t>(K) * Rp;
+    const int k0 = blockIdx.z * kper;
+    const int k1 = min(K, k0 + kper);
+    for (int k = k0; k < k1; ++k) {
+        const size_t idx = static_cast<size_t>(k) * Rp + col;
+        const int last = ss.last[idx];
+        const int kend = last >= n1 ? n1 : last + 1;
+        const int kc = kend - tb;
+        if (kc <= 0) continue;
+        cpx<T> *Xk = X + static_cast<size_t>(k) * ldx + static_cast<size_t>(col) * N;
+        cpx<T> *Pk = P + static_cast<size_t>(k) * ldp + static_cast<size_t>(col) * N;
+        cpx<T> pv[E], xv[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = ibase + e * kBlock;
+            pv[e] = i < N ? Pk[i] : cpx<T>{0, 0};
+            xv[e] = i < N ? Xk[i] : cpx<T>{0, 0};
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            if (j < kc) {
+                const size_t s = static_cast<size_t>((tb + j) % m) * KR + idx;
+                const cpx<T> a = ccast<T>(ss.ra[s]), b = ccast<T>(ss.rb[s]), cc = ccast<T>(ss.rc[s]);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    pv[e] = a * rr[j][e] + b * pv[e];
+                    xv[e] = xv[e] + cc * pv[e];
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = ibase + e * kBlock;
+            if (i < N) { Pk[i] = pv[e]; Xk[i] = xv[e]; }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ projected carry
+// g_{k,m} += c^k h_{k,m},  h_{k,m} <- a^k (c_m^T r') + b^k h_{k,m}  for the
+// projections c_m = e_{idx} (unit) and optionally c = S e_a, a = rhs[c] (srow).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_proj_update(int K, int Rp, int Mu, int srow, int slot, int B,
+                                                        const int32_t *rowptr, const int32_t *colidx,
+                                                        const double *Sval, const int64_t *rhs,
+                                                        const int32_t *pidx, ColState cs, ShiftState ss,
+                                                        const cpx<T> *rp, c128 *h, c128 *gacc) {
+    extern __shared__ c128 cr[];
+    const int c = blockIdx.x;
+    if (cs.done[c]) return;
+    const int M = Mu + srow;
+    for (int m = threadIdx.x; m < Mu; m += kBlock)
+        cr[m] = ccast<double>(rp[static_cast<size_t>(pidx[static_cast<size_t>(c) * Mu + m]) * Rp + c]);
+    if (srow) {
+        __shared__ c128 lds[kBlock];
+        const int64_t a = rhs[c];
+        const int I = static_cast<int>(a / B), ar = static_cast<int>(a % B);
+        const int b0 = rowptr[I], b1 = rowptr[I + 1];
+        c128 acc{0, 0};
+        for (int t = threadIdx.x; t < (b1 - b0) * B; t += kBlock) {
+            const int b = b0 + t / B, cc = t % B;
+            const double s = Sval[(static_cast<size_t>(b) * B + ar) * B + cc];
+            acc = acc + s * ccast<double>(rp[static_cast<size_t>(colidx[b] * B + cc) * Rp + c]);
+        }
+        const c128 tot = block_sum(acc, lds);
+        if (threadIdx.x == 0) cr[Mu] = tot;
+    }
+    __syncthreads();
+    const size_t KR = static_cast<size_t>(K) * Rp;
+    for (int t = threadIdx.x; t < K * M; t += kBlock) {
+        const int k = t / M, m = t % M;
+        const size_t idx = static_cast<size_t>(k) * Rp + c;
+        if (ss.last[idx] != kFrozenNever) continue;
+        const size_t s = static_cast<size_t>(slot) * KR + idx;
+        const size_t o = idx * M + m;
+        const c128 hv = ss.ra[s] * cr[m] + ss.rb[s] * h[o];
+        h[o] = hv;
+        gacc[o] = gacc[o] + ss.rc[s] * hv;
+    }
+}
+
+// ------------------------------------------------------------------ outputs
+// (S x^k)_a for unit rhs a = rhs[c] from the full-carry iterates.
+template <typename T>
+__global__ void k_sx_diag(int K, int R, int N, int B, const int32_t *rowptr, const int32_t *colidx,
+                          const double *Sval, const int64_t *rhs, const cpx<T> *X, size_t ldk,
+                          c128 *out, int ldo, int r0) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(K) * R) return;
+    const int k = static_cast<int>(t / R), c = static_cast<int>(t % R);
+    const int64_t a = rhs[c];
+    const int I = static_cast<int>(a / B), ar = static_cast<int>(a % B);
+    const cpx<T> *x = X + static_cast<size_t>(k) * ldk + static_cast<size_t>(c) * N;
+    c128 acc{0, 0};
+    for (int b = rowptr[I]; b < rowptr[I + 1]; ++b)
+        for (int cc = 0; cc < B; ++cc)
+            acc = acc + Sval[(static_cast<size_t>(b) * B + ar) * B + cc] * ccast<double>(x[colidx[b] * B + cc]);
+    out[static_cast<size_t>(k) * ldo + r0 + c] = acc;
+}
+
+template <typename T>
+__global__ void k_gather_proj(int K, int R, int N, int np, const int32_t *pidx, const cpx<T> *X, size_t ldk,
+                              c128 *out, int nrhs_total, int r0) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(K) * R * np) return;
+    const int m = static_cast<int>(t % np);
+    const int c = static_cast<int>((t / np) % R);
+    const int k = static_cast<int>(t / (static_cast<int64_t>(np) * R));
+    const int i = pidx[static_cast<size_t>(c) * np + m];
+    out[(static_cast<size_t>(k) * nrhs_total + r0 + c) * np + m] =
+        ccast<double>(X[static_cast<size_t>(k) * ldk + static_cast<size_t>(c) * N + i]);
+}
+
+// copy / widen the tile's x^k into the caller's [K][nrhs][N] complex128 layout
+template <typename T>
+__global__ void k_store_cols(int K, int R, int N, const cpx<T> *X, size_t ldk, c128 *out, int nrhs_total,
+                             int r0) {
+    const int64_t per = static_cast<int64_t>(R) * N;
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= per * K) return;
+    const int64_t k = t / per, o = t % per;
+    out[(k * nrhs_total + r0) * N + o] = ccast<double>(X[k * ldk + o]);
+}
+
+__global__ void k_store_proj(int K, int R, int Rp, int M, const c128 *g, c128 *out, int nrhs_total, int r0) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(K) * R * M) return;
+    const int m = static_cast<int>(t % M);
+    const int c = static_cast<int>((t / M) % R);
+    const int k = static_cast<int>(t / (static_cast<int64_t>(M) * R));
+    out[(static_cast<size_t>(k) * nrhs_total + r0 + c) * M + m] = g[(static_cast<size_t>(k) * Rp + c) * M + m];
+}
+
+// FP64 true residual ||b - (z_k S - H) x_k||^2 (partial per (k, c) by rows)
+template <typename T>
+__global__ void k_true_residual(int K, int R, int N, int B, const int32_t *rowptr, const int32_t *colidx,
+                                const double *Sval, const double *Hval, const c128 *z, const int64_t *rhs,
+                                const c128 *Bd, const cpx<T> *X, size_t ldk, double *out) {
+    // one block per (k, c); threads stride rows
+    __shared__ double lds[kBlock];
+    const int k = blockIdx.y, c = blockIdx.x;
+    const cpx<T> *x = X + static_cast<size_t>(k) * ldk + static_cast<size_t>(c) * N;
+    const c128 zk = z[k];
+    double acc = 0.0, bb = 0.0;
+    for (int i = threadIdx.x; i < N; i += kBlock) {
+        const int I = i / B, ar = i % B;
+        c128 s{0, 0}, h{0, 0};
+        for (int b = rowptr[I]; b < rowptr[I + 1]; ++b)
+            for (int cc = 0; cc < B; ++cc) {
+                const c128 xv = ccast<double>(x[colidx[b] * B + cc]);
+                s = s + Sval[(static_cast<size_t>(b) * B + ar) * B + cc] * xv;
+                h = h + Hval[(static_cast<size_t>(b) * B + ar) * B + cc] * xv;
+            }
+        c128 bv{0, 0};
+        if (rhs != nullptr) bv = (i == rhs[c]) ? c128{1, 0} : c128{0, 0};
+        else bv = Bd[static_cast<size_t>(c) * N + i];
+        const c128 rv = bv - (zk * s - h);
+        acc += cabs2(rv);
+        bb += cabs2(bv);
+    }
+    const double ta = block_sum(acc, lds);
+    const double tb = block_sum(bb, lds);
+    if (threadIdx.x == 0) out[static_cast<size_t>(k) * R + c] = sqrt(ta) / sqrt(tb);
+}
+
+// ------------------------------------------------------------------ driver
+namespace {
+
+int pick_groups(int64_t rows, int colchunks, int target_blocks) {
+    int g = std::max(1, target_blocks / std::max(1, colchunks));
+    g = static_cast<int>(std::min<int64_t>(g, (rows + 3) / 4));
+    g = std::max(g, 1);
+    g = (g + 7) / 8 * 8;
+    return g;
+}
+
+template <typename T> struct Tile {
+    TileDims td{};
+    DevBuf<cpx<T>> p, q, r, res, d, w, ring;
+    DevBuf<cpx<T>> Xown, P;
+    cpx<T> *X = nullptr;
+    size_t ldk = 0;
+    // column state
+    DevBuf<c128> c_rho, c_alpha, c_alpha_prev, c_beta_prev, c_swc, c_swcm;
+    DevBuf<double> c_bnorm, c_rnorm2, c_rr, c_rr_stop, c_cg_a, c_cg_b;
+    DevBuf<int> c_seed, c_done, c_inner_done, c_cg_first, c_sw, c_applied, c_flags, c_zres, c_inner_count,
+        c_iters;
+    DevBuf<long long> c_shift_iters;
+    // shift state
+    DevBuf<c128> s_pi, s_pi_prev, s_pi_next, s_omega, s_ra, s_rb, s_rc;
+    DevBuf<double> s_res;
+    DevBuf<int> s_last;
+    // partials
+    DevBuf<c128> part_c;
+    DevBuf<double> part_d;
+    // projected carry
+    DevBuf<c128> h, gacc;
+    DevBuf<int32_t> pidx;
+    int Mu = 0, srow = 0;
+
+    ColState cols() {
+        ColState c{};
+        c.rho = c_rho.get(); c.alpha = c_alpha.get(); c.alpha_prev = c_alpha_prev.get();
+        c.beta_prev = c_beta_prev.get(); c.swc = c_swc.get(); c.swcm = c_swcm.get();
+        c.bnorm = c_bnorm.get(); c.rnorm2 = c_rnorm2.get(); c.rr = c_rr.get(); c.rr_stop = c_rr_stop.get();
+        c.cg_a = c_cg_a.get(); c.cg_b = c_cg_b.get(); c.seed = c_seed.get(); c.done = c_done.get();
+        c.inner_done = c_inner_done.get(); c.cg_first = c_cg_first.get(); c.sw = c_sw.get();
+        c.applied = c_applied.get(); c.flags = c_flags.get(); c.zres = c_zres.get();
+        c.inner_count = c_inner_count.get(); c.shift_iters = c_shift_iters.get(); c.iters = c_iters.get();
+        return c;
+    }
+    ShiftState shifts(const c128 *z) {
+        ShiftState s{};
+        s.z = z; s.pi = s_pi.get(); s.pi_prev = s_pi_prev.get(); s.pi_next = s_pi_next.get();
+        s.omega = s_omega.get(); s.res = s_res.get(); s.last = s_last.get();
+        s.ra = s_ra.get(); s.rb = s_rb.get(); s.rc = s_rc.get();
+        return s;
+    }
+};
+
+struct HostStatus {
+    Status *h = nullptr;
+    DevBuf<Status> d;
+    HostStatus() {
+        GSC_HIP(hipHostMalloc(reinterpret_cast<void **>(&h), sizeof(Status), hipHostMallocDefault));
+        d.alloc(1);
+    }
+    ~HostStatus() {
+        if (h) (void)hipHostFree(h);
+    }
+};
+
+template <typename T> class TileSolver {
+  public:
+    TileSolver(Ctx &ctx, const SolveRequest &req, const c128 *dz, const int64_t *drhs, const c128 *dB,
+               int r0, int R, int Rp, int m, bool full)
+        : ctx_(ctx), req_(req), pr_(*req.pair), dz_(dz), drhs_(drhs), dB_(dB), r0_(r0), full_(full) {
+        auto &td = t_.td;
+        td.N = static_cast<int>(pr_.n);
+        td.nb = static_cast<int>(pr_.nb);
+        td.B = pr_.B;
+        td.K = req.K;
+        td.R = R;
+        td.Rp = Rp;
+        td.m = m;
+        td.G = pick_groups(td.N, Rp / 64, 2048);
+        td.Lr = div_up(td.N, td.G);
+        td.Gs = pick_groups(td.nb, Rp / 64, 2048);
+        td.Lb = div_up(td.nb, td.Gs);
+        st_ = ctx_.stream;
+    }
+
+    void allocate() {
+        auto &td = t_.td;
+        const size_t NR = static_cast<size_t>(td.N) * td.Rp;
+        t_.p.alloc(NR); t_.q.alloc(NR); t_.r.alloc(NR); t_.res.alloc(NR); t_.d.alloc(NR); t_.w.alloc(NR);
+        t_.ring.alloc(NR * td.m);
+        const size_t Rp = td.Rp;
+        t_.c_rho.alloc(Rp); t_.c_alpha.alloc(Rp); t_.c_alpha_prev.alloc(Rp); t_.c_beta_prev.alloc(Rp);
+        t_.c_swc.alloc(Rp); t_.c_swcm.alloc(Rp);
+        t_.c_bnorm.alloc(Rp); t_.c_rnorm2.alloc(Rp); t_.c_rr.alloc(Rp); t_.c_rr_stop.alloc(Rp);
+        t_.c_cg_a.alloc(Rp); t_.c_cg_b.alloc(Rp);
+        t_.c_seed.alloc(Rp); t_.c_done.alloc(Rp); t_.c_inner_done.alloc(Rp); t_.c_cg_first.alloc(Rp);
+        t_.c_sw.alloc(Rp); t_.c_applied.alloc(Rp); t_.c_flags.alloc(Rp); t_.c_zres.alloc(Rp);
+        t_.c_inner_count.alloc(Rp); t_.c_iters.alloc(Rp); t_.c_shift_iters.alloc(Rp);
+        const size_t KR = static_cast<size_t>(td.K) * Rp;
+        t_.s_pi.alloc(KR); t_.s_pi_prev.alloc(KR); t_.s_pi_next.alloc(KR); t_.s_omega.alloc(KR);
+        t_.s_res.alloc(KR); t_.s_last.alloc(KR);
+        t_.s_ra.alloc(KR * td.m); t_.s_rb.alloc(KR * td.m); t_.s_rc.alloc(KR * td.m);
+        const size_t G = std::max(td.G, td.Gs);
+        t_.part_c.alloc(G * Rp);
+        t_.part_d.alloc(G * Rp);
+        if (full_) {
+            t_.ldk = static_cast<size_t>(td.R) * td.N;
+            t_.P.alloc(t_.ldk * td.K);
+            const bool direct = std::is_same<T, double>::value && req_.G_cols != nullptr &&
+                                req_.out_mem == GSC_MEM_DEVICE;
+            if (direct) {
+                t_.X = reinterpret_cast<cpx<T> *>(req_.G_cols) + static_cast<size_t>(r0_) * td.N;
+                ldk_x_ = static_cast<size_t>(req_.R) * td.N;
+            } else {
+                t_.Xown.alloc(t_.ldk * td.K);
+                t_.X = t_.Xown.get();
+                ldk_x_ = t_.ldk;
+            }
+        }
+        if (req_.proj != nullptr) {
+            const ProjSpec &ps = *req_.proj;
+            t_.Mu = ps.M;
+            t_.srow = (ps.srow && drhs_ != nullptr) ? 1 : 0;
+            const int M = t_.Mu + t_.srow;
+            t_.h.alloc(KR * M);
+            t_.gacc.alloc(KR * M);
+            if (t_.Mu > 0) {
+                std::vector<int32_t> idx(static_cast<size_t>(td.Rp) * t_.Mu, 0);
+                for (int c = 0; c < td.R; ++c)
+                    for (int mm = 0; mm < t_.Mu; ++mm)
+                        idx[static_cast<size_t>(c) * t_.Mu + mm] =
+                            ps.idx[static_cast<size_t>(r0_ + c) * t_.Mu + mm];
+                t_.pidx.alloc(idx.size());
+                GSC_HIP(hipMemcpyAsync(t_.pidx.get(), idx.data(), idx.size() * sizeof(int32_t),
+                                       hipMemcpyHostToDevice, st_));
+            }
+        }
+    }
+
+    // Runs the whole iteration; returns the number of outer iterations.
+    int run(const gsc_opts &o, double inner_tol, int seed0) {
+        auto &td = t_.td;
+        ColState cs = t_.cols();
+        ShiftState ss = t_.shifts(dz_);
+        const dim3 eg(td.Rp / 64, td.G), eb(kBlock);
+        const int cb = div_up(td.Rp, 256);
+        const size_t NR = static_cast<size_t>(td.N) * td.Rp;
+        k_init_cols<<<cb, 256, 0, st_>>>(td.R, td.Rp, seed0, cs);
+        k_init_shifts<<<div_up(static_cast<int64_t>(td.K) * td.Rp, 256), 256, 0, st_>>>(td.K, td.R, td.Rp, ss);
+        if (full_) {
+            const int64_t tot = static_cast<int64_t>(td.R) * td.N * td.K;
+            k_zero_shifted<T><<<div_up(tot, 256), 256, 0, st_>>>(td.K, td.R, td.N, t_.ldk, t_.P.get());
+            k_zero_shifted<T><<<div_up(tot, 256), 256, 0, st_>>>(td.K, td.R, td.N, ldk_x_, t_.X);
+        }
+        if (t_.h.get()) {
+            GSC_HIP(hipMemsetAsync(t_.h.get(), 0, t_.h.n * sizeof(c128), st_));
+            GSC_HIP(hipMemsetAsync(t_.gacc.get(), 0, t_.gacc.n * sizeof(c128), st_));
+        }
+        GSC_HIP(hipGetLastError());
+        // r = b, r'_0 = S^{-1} b, p = r'_0, rho = r'^T r
+        k_init_rhs<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, td.R, drhs_, dB_, t_.r.get(), t_.res.get(),
+                                         t_.d.get(), t_.part_d.get());
+        k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 1, inner_tol, cs);
+        inner_solve(o, cs, t_.ring.get());
+        k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), t_.ring.get(),
+                                        t_.r.get(), t_.part_c.get());
+        k_init_rho<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_c.get(), cs);
+        k_p_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, 1, cs, t_.ring.get(), t_.r.get(), t_.p.get(),
+                                         t_.P.get(), t_.ldk);
+        GSC_HIP(hipGetLastError());
+        check_status(false);
+
+        const T *Sv = sval(), *Hv = hval();
+        int n0 = 0;   // first unflushed step (full carry)
+        int n = 0;
+        for (; n < o.max_iter; ++n) {
+            const int slot = n % td.m, slot_next = (n + 1) % td.m;
+            cpx<T> *rp_n = t_.ring.get() + slot * NR;
+            cpx<T> *rp_next = t_.ring.get() + slot_next * NR;
+            launch_spmm_seed<T>(st_, pr_, td, Sv, Hv, t_.p.get(), t_.q.get(), dz_, t_.c_seed.get(),
+                                t_.c_done.get(), t_.part_c.get());
+            k_ctrl<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.Gs, slot, t_.part_c.get(), cs, ss);
+            if (full_) {
+                if (n + 1 - n0 == td.m) {
+                    flush(cs, ss, n0, n + 1, 0);
+                    n0 = n + 1;
+                }
+            } else {
+                proj_update(cs, ss, slot, rp_n);
+            }
+            k_update_r<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_alpha.get(),
+                                             t_.q.get(), t_.r.get(), t_.res.get(), t_.d.get(), t_.part_d.get());
+            k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 0, inner_tol, cs);
+            inner_solve(o, cs, rp_next);
+            k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), rp_next,
+                                            t_.r.get(), t_.part_c.get());
+            k_post<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.G, n, full_ ? 1 : 0, t_.part_c.get(), o.tol, cs,
+                                              ss, t_.h.get(), t_.Mu + t_.srow);
+            GSC_HIP(hipGetLastError());
+            const Status s = check_status(true);
+            if (full_ && s.switched > 0) {
+                flush(cs, ss, n0, n + 1, 1);
+                k_mark_applied<<<cb, 256, 0, st_>>>(td.Rp, n + 1, cs);
+            }
+            k_p_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, 0, cs, rp_next, t_.r.get(), t_.p.get(),
+                                             t_.P.get(), t_.ldk);
+            if (s.active_cols == 0) { ++n; break; }
+        }
+        if (full_ && n > n0) flush(cs, ss, n0, n, 0);
+        GSC_HIP(hipGetLastError());
+        return n;
+    }
+
+    void write_outputs(gsc_stats *stats, double *res_host, unsigned char *conv_host, double tol, int nrhs_total) {
+        auto &td = t_.td;
+        (void)stats;
+        if (full_) {
+            if (req_.G_cols != nullptr && t_.X == t_.Xown.get()) {
+                if (req_.out_mem == GSC_MEM_DEVICE) {
+                    const int64_t tot = static_cast<int64_t>(td.R) * td.N * td.K;
+                    k_store_cols<T><<<div_up(tot, 256), 256, 0, st_>>>(
+                        td.K, td.R, td.N, t_.X, ldk_x_, reinterpret_cast<c128 *>(req_.G_cols), nrhs_total, r0_);
+                } else {
+                    // widen on the device, then copy each shift's slab
+                    DevBuf<c128> tmp(static_cast<size_t>(td.R) * td.N * td.K);
+                    const int64_t tot = static_cast<int64_t>(td.R) * td.N * td.K;
+                    k_store_cols<T><<<div_up(tot, 256), 256, 0, st_>>>(td.K, td.R, td.N, t_.X, ldk_x_, tmp.get(),
+                                                                      td.R, 0);
+                    GSC_HIP(hipGetLastError());
+                    for (int k = 0; k < td.K; ++k)
+                        GSC_HIP(hipMemcpyAsync(req_.G_cols + 2 * ((static_cast<size_t>(k) * nrhs_total + r0_) * td.N),
+                                               tmp.get() + static_cast<size_t>(k) * td.R * td.N,
+                                               static_cast<size_t>(td.R) * td.N * sizeof(c128),
+                                               hipMemcpyDeviceToHost, st_));
+                    GSC_HIP(hipStreamSynchronize(st_));
+                }
+            }
+            if (req_.G_proj != nullptr && req_.nproj > 0) {
+                std::vector<int32_t> idx(static_cast<size_t>(td.R) * req_.nproj);
+                for (int c = 0; c < td.R; ++c)
+                    for (int mm = 0; mm < req_.nproj; ++mm)
+                        idx[static_cast<size_t>(c) * req_.nproj + mm] =
+                            static_cast<int32_t>(req_.proj_idx[static_cast<size_t>(r0_ + c) * req_.nproj + mm]);
+                DevBuf<int32_t> didx(idx.size());
+                GSC_HIP(hipMemcpyAsync(didx.get(), idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                       st_));
+                const int64_t tot = static_cast<int64_t>(td.K) * td.R * req_.nproj;
+                if (req_.out_mem == GSC_MEM_DEVICE) {
+                    k_gather_proj<T><<<div_up(tot, 256), 256, 0, st_>>>(td.K, td.R, td.N, req_.nproj, didx.get(),
+                                                                       t_.X, ldk_x_,
+                                                                       reinterpret_cast<c128 *>(req_.G_proj),
+                                                                       nrhs_total, r0_);
+                    GSC_HIP(hipStreamSynchronize(st_));
+                } else {
+                    DevBuf<c128> tmp(static_cast<size_t>(td.K) * td.R * req_.nproj);
+                    k_gather_proj<T><<<div_up(tot, 256), 256, 0, st_>>>(td.K, td.R, td.N, req_.nproj, didx.get(),
+                                                                       t_.X, ldk_x_, tmp.get(), td.R, 0);
+                    std::vector<c128> h(tmp.n);
+                    GSC_HIP(hipMemcpyAsync(h.data(), tmp.get(), h.size() * sizeof(c128), hipMemcpyDeviceToHost,
+                                           st_));
+                    GSC_HIP(hipStreamSynchronize(st_));
+                    for (int k = 0; k < td.K; ++k)
+                        for (int c = 0; c < td.R; ++c)
+                            std::memcpy(req_.G_proj + 2 * ((static_cast<size_t>(k) * nrhs_total + r0_ + c) * req_.nproj),
+                                        h.data() + (static_cast<size_t>(k) * td.R + c) * req_.nproj,
+                                        req_.nproj * sizeof(c128));
+                }
+                GSC_HIP(hipGetLastError());
+            }
+            if (req_.sg_diag != nullptr) {
+                const int64_t tot = static_cast<int64_t>(td.K) * td.R;
+                k_sx_diag<T><<<div_up(tot, 256), 256, 0, st_>>>(td.K, td.R, td.N, td.B, pr_.rowptr.get(),
+                                                               pr_.colidx.get(), pr_.S.get(), drhs_, t_.X, ldk_x_,
+                                                               req_.sg_diag, nrhs_total, r0_);
+                GSC_HIP(hipGetLastError());
+            }
+        } else if (req_.proj_out != nullptr) {
+            const int M = t_.Mu + t_.srow;
+            const int64_t tot = static_cast<int64_t>(td.K) * td.R * M;
+            k_store_proj<<<div_up(tot, 256), 256, 0, st_>>>(td.K, td.R, td.Rp, M, t_.gacc.get(), req_.proj_out,
+                                                            nrhs_total, r0_);
+            GSC_HIP(hipGetLastError());
+        }
+        // per (k, r) residual estimates
+        std::vector<double> res(static_cast<size_t>(td.K) * td.Rp);
+        GSC_HIP(hipMemcpyAsync(res.data(), t_.s_res.get(), res.size() * sizeof(double), hipMemcpyDeviceToHost, st_));
+        std::vector<long long> si(td.Rp);
+        std::vector<int> inner(td.Rp), iters(td.Rp);
+        GSC_HIP(hipMemcpyAsync(si.data(), t_.c_shift_iters.get(), si.size() * sizeof(long long),
+                               hipMemcpyDeviceToHost, st_));
+        GSC_HIP(hipStreamSynchronize(st_));
+        for (int k = 0; k < td.K; ++k)
+            for (int c = 0; c < td.R; ++c) {
+                const double v = res[static_cast<size_t>(k) * td.Rp + c];
+                if (res_host) res_host[static_cast<size_t>(k) * nrhs_total + r0_ + c] = v;
+                if (conv_host) conv_host[static_cast<size_t>(k) * nrhs_total + r0_ + c] = v <= tol ? 1 : 0;
+                worst_res_ = std::max(worst_res_, v);
+            }
+        for (int c = 0; c < td.R; ++c) shift_rhs_iters_ += si[c];
+    }
+
+    void true_residual(double *out_host, int nrhs_total) {
+        auto &td = t_.td;
+        DevBuf<double> out(static_cast<size_t>(td.K) * td.R);
+        dim3 grid(td.R, td.K);
+        k_true_residual<T><<<grid, kBlock, 0, st_>>>(td.K, td.R, td.N, td.B, pr_.rowptr.get(), pr_.colidx.get(),
+                                                    pr_.S.get(), pr_.H.get(), dz_, drhs_, dB_, t_.X, ldk_x_,
+                                                    out.get());
+        GSC_HIP(hipGetLastError());
+        std::vector<double> h(out.n);
+        GSC_HIP(hipMemcpyAsync(h.data(), out.get(), h.size() * sizeof(double), hipMemcpyDeviceToHost, st_));
+        GSC_HIP(hipStreamSynchronize(st_));
+        for (int k = 0; k < td.K; ++k)
+            for (int c = 0; c < td.R; ++c)
+                out_host[static_cast<size_t>(k) * nrhs_total + r0_ + c] = h[static_cast<size_t>(k) * td.R + c];
+    }
+
+    long long inner_total() const { return inner_total_; }
+    int switches() const { return switches_; }
+    long long shift_rhs_iters() const { return shift_rhs_iters_; }
+    double worst_res() const { return worst_res_; }
+    int flags() const { return flags_; }
+
+  private:
+    const T *sval() const;
+    const T *hval() const;
+
+    Status check_status(bool count_switch) {
+        auto &td = t_.td;
+        k_status<<<1, kBlock, 0, st_>>>(td.Rp, t_.cols(), hs_.d.get());
+        GSC_HIP(hipGetLastError());
+        GSC_HIP(hipMemcpyAsync(hs_.h, hs_.d.get(), sizeof(Status), hipMemcpyDeviceToHost, st_));
+        GSC_HIP(hipStreamSynchronize(st_));
+        const Status s = *hs_.h;
+        flags_ |= s.flags;
+        if (count_switch) switches_ += s.switched;
+        if (s.flags & FLAG_NAN) throw Error(GSC_E_NAN, "non-finite value in the iteration");
+        if (s.flags & FLAG_NOT_SPD) throw Error(GSC_E_S_NOT_SPD, "inner CG found d^H S d <= 0: S is not positive definite");
+        if (s.flags & FLAG_BREAKDOWN) throw Error(GSC_E_BREAKDOWN, "COCG breakdown (p^T A p or r'^T r vanished)");
+        return s;
+    }
+
+    void inner_solve(const gsc_opts &o, ColState cs, cpx<T> *y) {
+        auto &td = t_.td;
+        const dim3 eg(td.Rp / 64, td.G), eb(kBlock);
+        int done_steps = 0;
+        int chunk = inner_guess_;
+        const T *Sv = sval();
+        while (true) {
+            for (int j = 0; j < chunk; ++j) {
+                launch_spmm_S<T>(st_, pr_, td, Sv, t_.d.get(), t_.w.get(), t_.c_inner_done.get(), t_.part_d.get());
+                k_cg_a<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), cs);
+                k_cg_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_inner_done.get(), t_.c_cg_first.get(),
+                                                  t_.c_cg_a.get(), t_.d.get(), t_.w.get(), y, t_.res.get(),
+                                                  t_.part_d.get());
+                k_cg_b<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), o.inner_max_iter, cs);
+                k_cg_dir<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_inner_done.get(), t_.c_cg_b.get(),
+                                               t_.res.get(), t_.d.get());
+            }
+            GSC_HIP(hipGetLastError());
+            done_steps += chunk;
+            const Status s = check_status(false);
+            if (s.inner_pending == 0 || done_steps >= o.inner_max_iter) break;
+            chunk = 2;
+        }
+        inner_total_ += done_steps;
+        inner_guess_ = std::max(1, done_steps);
+    }
+
+    void flush(ColState cs, ShiftState ss, int n0, int n1, int only_sw) {
+        auto &td = t_.td;
+        constexpr int E = 2;
+        const int kper = std::max(1, std::min(td.K, 64));
+        dim3 grid(div_up(td.N, kBlock * E), td.R, div_up(td.K, kper));
+        const size_t NR = static_cast<size_t>(td.N) * td.Rp;
+#define GSC_FLUSH(MM)                                                                                    \
+    k_flush<T, MM, E><<<grid, kBlock, 0, st_>>>(td.N, td.Rp, td.K, td.m, n0, n1, only_sw, kper, cs, ss, \
+                                                t_.ring.get(), NR, t_.X, ldk_x_, t_.P.get(), t_.ldk)
+        if (td.m <= 1) GSC_FLUSH(1);
+        else if (td.m <= 2) GSC_FLUSH(2);
+        else if (td.m <= 4) GSC_FLUSH(4);
+        else if (td.m <= 8) GSC_FLUSH(8);
+        else GSC_FLUSH(16);
+#undef GSC_FLUSH
+        GSC_HIP(hipGetLastError());
+    }
+
+    void proj_update(ColState cs, ShiftState ss, int slot, const cpx<T> *rp) {
+        auto &td = t_.td;
+        const int M = t_.Mu + t_.srow;
+        const size_t shm = static_cast<size_t>(M) * sizeof(c128);
+        k_proj_update<T><<<td.Rp, kBlock, shm, st_>>>(td.K, td.Rp, t_.Mu, t_.srow, slot, td.B, pr_.rowptr.get(),
+                                                     pr_.colidx.get(), pr_.S.get(), drhs_, t_.pidx.get(), cs, ss,
+                                                     rp, t_.h.get(), t_.gacc.get());
+        GSC_HIP(hipGetLastError());
+    }
+
+    Ctx &ctx_;
+    const SolveRequest &req_;
+    const Pair &pr_;
+    const c128 *dz_;
+    const int64_t *drhs_;
+    const c128 *dB_;
+    int r0_;
+    bool full_;
+    hipStream_t st_;
+    Tile<T> t_;
+    size_t ldk_x_ = 0;
+    HostStatus hs_;
+    int inner_guess_ = 8;
+    long long inner_total_ = 0;
+    int switches_ = 0;
+    long long shift_rhs_iters_ = 0;
+    double worst_res_ = 0.0;
+    int flags_ = 0;
+};
+
+template <> const double *TileSolver<double>::sval() const { return pr_.S.get(); }
+template <> const double *TileSolver<double>::hval() const { return pr_.H.get(); }
+template <> const float *TileSolver<float>::sval() const { return pr_.S32.get(); }
+template <> const float *TileSolver<float>::hval() const { return pr_.H32.get(); }
+
+int default_seed(const std::vector<double> &z, int K) {
+    double lo = z[0], hi = z[0];
+    for (int k = 0; k < K; ++k) { lo = std::min(lo, z[2 * k]); hi = std::max(hi, z[2 * k]); }
+    const double mid = 0.5 * (lo + hi);
+    int best = 0;
+    for (int k = 1; k < K; ++k)
+        if (std::fabs(z[2 * k] - mid) < std::fabs(z[2 * best] - mid)) best = k;
+    return best;
+}
+
+template <typename T>
+gsc_status solve_typed(Ctx &ctx, SolveRequest &req) {
+    const Pair &pr = *req.pair;
+    const gsc_opts &o = req.opts;
+    hipStream_t st = ctx.stream;
+    const int N = static_cast<int>(pr.n);
+    const bool full = o.carry == GSC_CARRY_FULL;
+    std::vector<double> zh(req.z, req.z + 2 * req.K);
+    DevBuf<c128> dz(req.K);
+    GSC_HIP(hipMemcpyAsync(dz.get(), zh.data(), zh.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    const int seed0 = o.seed_index >= 0 ? o.seed_index : default_seed(zh, req.K);
+    double inner_tol = o.inner_tol > 0 ? o.inner_tol : std::max(1e-2 * o.tol, 1e-15);
+
+    // tile width: all rhs if memory allows
+    int Rt = o.rhs_tile > 0 ? o.rhs_tile : req.R;
+    if (full && o.rhs_tile <= 0) {
+        size_t freeb = 0, totalb = 0;
+        GSC_HIP(hipMemGetInfo(&freeb, &totalb));
+        const double per_col = 2.0 * req.K * N * sizeof(cpx<T>) + 16.0 * N * sizeof(cpx<T>);
+        const int fit = static_cast<int>(0.8 * static_cast<double>(freeb) / per_col);
+        Rt = std::max(1, std::min(Rt, fit));
+    }
+    Rt = std::max(1, std::min(Rt, req.R));
+    int m = o.fuse_steps > 0 ? std::min(o.fuse_steps, kMaxFuse) : (full ? 8 : 1);
+    if (!full) m = 1;
+
+    std::vector<double> res_tmp;
+    double *res_host = req.stats ? req.stats->res_recursive : nullptr;
+    unsigned char *conv_host = req.stats ? req.stats->converged : nullptr;
+    if (res_host == nullptr) {
+        res_tmp.resize(static_cast<size_t>(req.K) * req.R);
+        res_host = res_tmp.data();
+    }
+    hipEvent_t e0, e1;
+    GSC_HIP(hipEventCreate(&e0));
+    GSC_HIP(hipEventCreate(&e1));
+    GSC_HIP(hipEventRecord(e0, st));
+    int max_iters = 0, switches = 0;
+    long long inner = 0, sri = 0;
+    bool all_conv = true;
+    for (int r0 = 0; r0 < req.R; r0 += Rt) {
+        const int R = std::min(Rt, req.R - r0);
+        const int Rp = (R + 63) / 64 * 64;
+        DevBuf<int64_t> drhs;
+        if (req.rhs_idx != nullptr) {
+            std::vector<int64_t> h(Rp, 0);
+            for (int c = 0; c < R; ++c) h[c] = req.rhs_idx[r0 + c];
+            drhs.alloc(Rp);
+            GSC_HIP(hipMemcpyAsync(drhs.get(), h.data(), Rp * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        }
+        DevBuf<c128> dB;
+        const c128 *Bptr = nullptr;
+        if (req.rhs_idx == nullptr) {
+            if (req.out_mem == GSC_MEM_DEVICE) {
+                Bptr = reinterpret_cast<const c128 *>(req.B_dense) + static_cast<size_t>(r0) * N;
+            } else {
+                dB.alloc(static_cast<size_t>(R) * N);
+                GSC_HIP(hipMemcpyAsync(dB.get(), req.B_dense + 2 * static_cast<size_t>(r0) * N,
+                                       static_cast<size_t>(R) * N * sizeof(c128), hipMemcpyHostToDevice, st));
+                Bptr = dB.get();
+            }
+        }
+        TileSolver<T> ts(ctx, req, dz.get(), drhs.get(), Bptr, r0, R, Rp, m, full);
+        ts.allocate();
+        const int it = ts.run(o, inner_tol, seed0);
+        ts.write_outputs(req.stats, res_host, conv_host, o.tol, req.R);
+        if (full && req.stats && req.stats->res_true) ts.true_residual(req.stats->res_true, req.R);
+        max_iters = std::max(max_iters, it);
+        inner += ts.inner_total();
+        switches += ts.switches();
+        sri += ts.shift_rhs_iters();
+        if (ts.worst_res() > o.tol) all_conv = false;
+    }
+    GSC_HIP(hipEventRecord(e1, st));
+    GSC_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    GSC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (req.stats) {
+        req.stats->outer_iters = max_iters;
+        req.stats->inner_iters = inner;
+        req.stats->switches = switches;
+        req.stats->restarts = full ? 0 : switches;
+        req.stats->shift_rhs_iters = sri;
+        req.stats->seconds = ms * 1e-3;
+    }
+    return all_conv ? GSC_OK : GSC_NOT_CONVERGED;
+}
+
+}  // namespace
+
+gsc_status run_solve(Ctx &ctx, SolveRequest &req) {
+    if (req.opts.precision == GSC_MIXED) {
+        ensure_f32(const_cast<Pair &>(*req.pair));
+        return solve_typed<float>(ctx, req);
+    }
+    return solve_typed<double>(ctx, req);
+}
+
+}  // namespace gsc
