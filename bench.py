@@ -1,0 +1,191 @@
+"""Throughput of the generalized shifted COCG hot path on one MI355X.
+
+One step = ASED pair build on the device (eq. Hap-1) + the shifted solve of
+(z_k S - H) x = e_j for every shift and right-hand side (seed COCG, pi
+recurrence, fused shift updates, inner CG for S^{-1} r, seed switching),
+with the Green's-function columns left in HBM.  The default workload is
+si4096: Si diamond 8x8x8 cells (4096 atoms, N = 16384, 69,632 4x4 blocks),
+Gaussian displacements 0.05 A, 256 shifts on [-20, 5] eV with eta 0.05 eV,
+256 right-hand sides (all orbitals of 64 random atoms), FP64, tol 1e-10.
+
+Prints one JSON line.  The roofline object reports the dominant kernel's
+algorithmic bytes (counted on the device per launch) over its HIP-event time
+measured live on the library's stream during the timed steps.  The CPU
+baseline times the step-by-step oracle model of the same method on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "shift·RHS·iterations/s + HBM GB/s; mixed-batched vs plain FP64 at 1e-6"
+UNIT = "shift·RHS·iterations/s"
+
+
+def workload(name):
+    from synth import configs
+    if name == "si4096":
+        return configs.si4096()
+    if name == "si64":
+        return configs.si64()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def describe(cfg, args):
+    s = cfg["system"]
+    return {
+        "workload": cfg["name"],
+        "system": f"{s.n_atoms} atoms, N={s.n}, nnzb={s.nnzb}, block={s.block}",
+        "shifts": int(len(cfg["z"])),
+        "rhs": int(len(cfg["rhs"])),
+        "eta": float(cfg["z"][0].imag),
+        "tol": args.tol,
+        "carry": "full",
+        "fuse_steps": args.fuse,
+        "spmm_kernel": args.spmm,
+        "precision": args.precision,
+        "parallelism": "1 GPU",
+    }
+
+
+def cpu_baseline(cfg, iters):
+    """Oracle model of the method (oracle/shifted_cocg.py) on one rhs and all
+    shifts of the workload, for a fixed number of outer iterations."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ased, green, shifted_cocg
+
+    s = cfg["system"]
+    Sb, Hb, _ = ased.pair_blocks(s)
+    S, H = green.sparse_matrices(s, Sb, Hb)
+    b = np.zeros(s.n)
+    b[int(cfg["rhs"][0])] = 1.0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        r = shifted_cocg.solve(H, S, cfg["z"], b, tol=1e-10, max_iter=iters)
+        dt = time.perf_counter() - t0
+    return {"value": r.active_shift_iters / dt, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"oracle step-by-step model (numpy/scipy, 1 thread), workload {cfg['name']}, "
+                      f"1 rhs x {len(cfg['z'])} shifts x {r.iters} outer iterations "
+                      f"({r.active_shift_iters} active shift-iterations, {r.inner_iters} inner CG "
+                      f"steps) in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="si4096")
+    ap.add_argument("--fuse", type=int, default=8)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=60)
+    ap.add_argument("--spmm", type=int, default=0, help="0 auto, 1 row kernel, 2 cluster kernel")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no collectives, no sharding); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1002_1202_amd import api
+
+    cfg = workload(args.workload)
+    if args.tol is None:
+        args.tol = cfg["tol"]
+    s = cfg["system"]
+    z, rhs = cfg["z"], cfg["rhs"]
+    K, R, N = len(z), len(rhs), s.n
+    ctx = api.Context(0)
+    pair = api.Pair(ctx, s.block, s.rowptr, s.colidx)
+    Gc = torch.empty((K, R, N), dtype=torch.complex128, device="cuda:0")
+
+    def step():
+        api.ased_build(ctx, pair, s)
+        return api.solve(ctx, pair, z, rhs=rhs, out="device", out_cols=Gc, tol=args.tol,
+                         fuse_steps=args.fuse, precision=args.precision, spmm_kernel=args.spmm)
+
+    # warmup; the first warmup step times every kernel to find the dominant one
+    dom = None
+    for i in range(max(args.warmup, 1)):
+        if i == 0:
+            api.profile_enable(ctx, True)
+        r = step()
+        if i == 0:
+            pw = api.profile_read(ctx)
+            dom = max(pw, key=lambda k: pw[k][0])
+            api.profile_enable(ctx, False)
+        print(f"warmup {i}: iters={r.outer_iters} switches={r.switches} "
+              f"inner={r.inner_iters} conv={r.converged.mean():.3f} dev_s={r.seconds:.3f}",
+              file=sys.stderr, flush=True)
+    print("warmup kernel split (ms): " + ", ".join(f"{k}={v[0]:.1f}" for k, v in pw.items() if v[1]),
+          file=sys.stderr, flush=True)
+    # timed steps: HIP events around the dominant kernel only
+    api.profile_enable(ctx, True, only=dom)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for i in range(args.steps):
+        r = step()
+        results.append(r)
+        print(f"step {i}: iters={r.outer_iters} switches={r.switches} dev_s={r.seconds:.3f}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = api.profile_read(ctx)
+    api.profile_enable(ctx, False)
+
+    work = sum(r.shift_rhs_iters for r in results)
+    value = work / dt
+    total_bytes = sum(v[2] for v in prof.values())
+    ms, launches, byts = prof[dom]
+    achieved = (byts / (ms * 1e-3)) / 1e9 if ms > 0 else 0.0
+    kernels = {k: {"warmup_ms": round(v[0], 3), "launches": v[1], "GB": round(v[2] / 1e9, 3),
+                   "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
+               for k, v in pw.items() if v[1] > 0}
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "c64-products/f64-recurrences",
+        "data": "synthetic",
+        "config": describe(cfg, args),
+        "hbm_gbs_algorithmic": total_bytes / dt / 1e9,
+        "outer_iters": results[-1].outer_iters,
+        "switches": results[-1].switches,
+        "inner_iters": results[-1].inner_iters,
+        "converged_frac": float(np.mean(results[-1].converged)),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "bytes_per_launch": byts / max(launches, 1),
+                     "avg_launch_ms": ms / max(launches, 1), "traffic": None},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

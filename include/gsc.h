@@ -84,7 +84,15 @@ typedef struct {
     int rhs_tile;          /* [0 = auto] right-hand sides per device tile      */
     int recheck;           /* [0] 1: FP64 true residual of every (k, rhs) into
                               gsc_stats.res_true (full carry only)             */
-    int reserved[8];
+    int spmm_kernel;       /* [0 = auto] 1: one block row per wave, 2: register-
+                              blocked clusters of block rows sharing x loads   */
+    int inner_method;      /* [0 = auto] inner solver for S r' = r: 1 CG (the
+                              first solve always runs CG), 2 Chebyshev on the
+                              interval of the first CG solve's Ritz values
+                              widened by 10 %, with a residual check and extra
+                              steps if the check fails; auto = 2 when the
+                              interval is positive, else 1                     */
+    int reserved[6];
 } gsc_opts;
 
 /* Statistics.  The three arrays are caller-owned HOST arrays of
@@ -219,6 +227,24 @@ gsc_status gsc_band_energy_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, c
                                const double *w, double grad_E, const gsc_opts *opts,
                                double *dHval, double *dSval, double *e_band, int mem,
                                gsc_stats *stats);
+
+/* ---- kernel timing ------------------------------------------------------- */
+/* Live per-kernel timing with HIP events recorded on the context's stream
+ * around every launch of the named kernels (for roofline reporting).
+ * gsc_profile_enable(ctx, 1) resets the counters and turns timing on.
+ * gsc_profile_read returns, for one kernel name ("spmm_seed", "spmm_S",
+ * "shift_update", "cg_update", "cg_dir", "update_r", "rho_dot", "p_update",
+ * "ctrl", "post", "proj_update", "cheb_step"), the summed device milliseconds, the
+ * number of launches and the summed algorithmic bytes those launches must
+ * move (the method's own reads and writes, no re-reads).  GSC_E_ARG for an
+ * unknown name. */
+gsc_status gsc_profile_enable(gsc_ctx *ctx, int on);
+/* Restrict the event timing to one kernel name (NULL: time every kernel);
+ * byte counting continues for all kernels.  Event pairs cost a few
+ * microseconds each, so timing one kernel keeps the run undisturbed. */
+gsc_status gsc_profile_select(gsc_ctx *ctx, const char *kernel);
+gsc_status gsc_profile_read(gsc_ctx *ctx, const char *kernel, double *total_ms, long long *launches,
+                            double *bytes);
 
 /* Many independent systems in one launch sequence (each system's shifts,
  * rhs and outputs as in gsc_problem; projected carry, G_jj and charges). */

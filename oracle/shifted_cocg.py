@@ -70,6 +70,7 @@ class Result:
     res: np.ndarray | None = None   # (K,) recursive residual estimates at exit
     converged: np.ndarray | None = None
     iters: int = 0
+    active_shift_iters: int = 0     # sum over iterations of the number of active shifts
     inner_iters: int = 0
     switches: int = 0
     restarts: int = 0
@@ -145,6 +146,7 @@ def solve(H, S, z, b, tol: float = 1e-10, max_iter: int = 2000, inner_tol=None,
             dbeta_k = 2.0 * beta_prev * (pi_prev / pi) * (dpi_prev * pi - pi_prev * dpi) / pi ** 2
         # shifted vectors (only the active shifts move)
         a = active
+        out.active_shift_iters += int(a.sum())
         if full:
             P_old = P[a].copy()
             P[a] = rp[None, :] / pi[a, None] + beta_k[a, None] * P[a]

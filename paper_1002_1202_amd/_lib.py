@@ -21,7 +21,8 @@ class Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("inner_tol", C.c_double),
                 ("inner_max_iter", C.c_int), ("precision", C.c_int), ("carry", C.c_int),
                 ("seed_index", C.c_int), ("fuse_steps", C.c_int), ("rhs_tile", C.c_int),
-                ("recheck", C.c_int), ("reserved", C.c_int * 8)]
+                ("recheck", C.c_int), ("spmm_kernel", C.c_int), ("inner_method", C.c_int),
+                ("reserved", C.c_int * 6)]
 
 
 class Stats(C.Structure):
@@ -71,7 +72,13 @@ SIGNATURES = {
     "gsc_band_energy_vjp": (C.c_int, [_VP, _VP, C.c_int, _DP, _DP, C.c_double, C.POINTER(Opts),
                                       _VP, _VP, _DP, C.c_int, C.POINTER(Stats)]),
     "gsc_solve_batched": (C.c_int, [_VP, C.c_int, C.POINTER(Problem), C.POINTER(Opts)]),
+    "gsc_profile_enable": (C.c_int, [_VP, C.c_int]),
+    "gsc_profile_select": (C.c_int, [_VP, C.c_char_p]),
+    "gsc_profile_read": (C.c_int, [_VP, C.c_char_p, _DP, C.POINTER(C.c_longlong), _DP]),
 }
+
+KERNELS = ("spmm_seed", "spmm_S", "shift_update", "cg_update", "cg_dir", "update_r", "rho_dot",
+           "p_update", "ctrl", "post", "proj_update", "cheb_step")
 
 _lib = None
 

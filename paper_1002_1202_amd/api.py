@@ -70,6 +70,24 @@ class Context:
             pass
 
 
+def profile_enable(ctx: Context, on: bool = True, only: str | None = None):
+    """Reset and enable (or disable) live HIP-event timing of every kernel, or
+    of the kernel named ``only``.  Algorithmic bytes are counted for all."""
+    L.check(ctx.lib.gsc_profile_enable(ctx.h, int(on)))
+    if on:
+        L.check(ctx.lib.gsc_profile_select(ctx.h, only.encode() if only else None))
+
+
+def profile_read(ctx: Context) -> dict:
+    """{kernel: (total_ms, launches, algorithmic_bytes)} since profile_enable."""
+    out = {}
+    for name in L.KERNELS:
+        ms, n, b = C.c_double(), C.c_longlong(), C.c_double()
+        L.check(ctx.lib.gsc_profile_read(ctx.h, name.encode(), C.byref(ms), C.byref(n), C.byref(b)))
+        out[name] = (ms.value, n.value, b.value)
+    return out
+
+
 class Pair:
     """Block-sparse H, S pair on the device (copies the pattern)."""
 
@@ -173,13 +191,16 @@ def spmm(ctx: Context, pair: Pair, X, alpha_S):
 
 
 def make_opts(tol=1e-10, max_iter=5000, inner_tol=0.0, inner_max_iter=200, precision="fp64",
-              carry="full", seed_index=-1, fuse_steps=0, rhs_tile=0, recheck=False) -> L.Opts:
+              carry="full", seed_index=-1, fuse_steps=0, rhs_tile=0, recheck=False,
+              spmm_kernel=0, inner_method=0) -> L.Opts:
     o = L.Opts()
     L.load().gsc_opts_default(C.byref(o))
     o.tol, o.max_iter, o.inner_tol, o.inner_max_iter = tol, max_iter, inner_tol, inner_max_iter
     o.precision = {"fp64": L.FP64, "mixed": L.MIXED}[precision]
     o.carry = {"full": L.CARRY_FULL, "projected": L.CARRY_PROJECTED}[carry]
     o.seed_index, o.fuse_steps, o.rhs_tile, o.recheck = seed_index, fuse_steps, rhs_tile, int(recheck)
+    o.spmm_kernel = spmm_kernel
+    o.inner_method = inner_method
     return o
 
 
@@ -211,7 +232,7 @@ def _stats(K, R, recheck):
 
 
 def solve(ctx: Context, pair: Pair, z, rhs=None, B=None, out: str = "host", want_cols: bool = True,
-          proj=None, **opt) -> SolveResult:
+          proj=None, out_cols=None, **opt) -> SolveResult:
     """(z_k S - H) x_k = b_r for all shifts and right-hand sides.
 
     ``rhs``: orbital indices of unit right-hand sides; ``B``: dense (R, N)
@@ -241,7 +262,11 @@ def solve(ctx: Context, pair: Pair, z, rhs=None, B=None, out: str = "host", want
     if mem == L.MEM_DEVICE:
         import torch
         dev = f"cuda:{ctx.device}"
-        if want_cols and carry_full:
+        if out_cols is not None:
+            if tuple(out_cols.shape) != (K, R, N) or out_cols.dtype != torch.complex128:
+                raise ValueError("out_cols must be a (K, R, N) complex128 device tensor")
+            Gc = out_cols
+        elif want_cols and carry_full:
             Gc = torch.empty((K, R, N), dtype=torch.complex128, device=dev)
         if P:
             Gp = torch.empty((K, R, P), dtype=torch.complex128, device=dev)

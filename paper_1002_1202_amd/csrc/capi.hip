@@ -92,6 +92,8 @@ void validate_opts(const gsc_opts &o) {
     GSC_REQUIRE(o.precision == GSC_FP64 || o.precision == GSC_MIXED, "unknown precision");
     GSC_REQUIRE(o.carry == GSC_CARRY_FULL || o.carry == GSC_CARRY_PROJECTED, "unknown carry mode");
     GSC_REQUIRE(o.fuse_steps >= 0 && o.fuse_steps <= kMaxFuse, "fuse_steps must be in [0, 16]");
+    GSC_REQUIRE(o.spmm_kernel >= 0 && o.spmm_kernel <= 2, "spmm_kernel must be 0, 1 or 2");
+    GSC_REQUIRE(o.inner_method >= 0 && o.inner_method <= 2, "inner_method must be 0, 1 or 2");
 }
 
 void validate_shifts(int nshift, const double *z, int seed_index) {
@@ -263,8 +265,7 @@ gsc_status gsc_spmm(gsc_ctx *ctx, const gsc_pair *pair, int nrhs, const double *
         GSC_HIP(hipMemcpyAsync(dseed.get(), iota.data(), Rp * sizeof(int), hipMemcpyHostToDevice, st));
         TileDims td{};
         td.N = N; td.nb = static_cast<int>(p.nb); td.B = p.B; td.Rp = Rp;
-        td.Gs = std::max(8, std::min<int>((2048 / (Rp / 64) + 7) / 8 * 8, (td.nb + 7) / 8 * 8));
-        td.Lb = div_up(td.nb, td.Gs);
+        set_spmm_geometry(td, p, 1);
         DevBuf<c128> part(static_cast<size_t>(td.Gs) * Rp);
         launch_spmm_seed<double>(st, p, td, p.S.get(), p.H.get(), xp.get(), yp.get(), dz.get(), dseed.get(),
                                  nullptr, part.get());
@@ -410,6 +411,50 @@ gsc_status gsc_band_energy_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, c
     (void)dHval; (void)dSval; (void)e_band; (void)mem; (void)stats;
     set_last_error("gsc_band_energy_vjp: not built yet");
     return GSC_E_UNSUPPORTED;
+}
+
+gsc_status gsc_profile_enable(gsc_ctx *ctx, int on) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+        DeviceGuard g(ctx->c.device);
+        GSC_HIP(hipStreamSynchronize(ctx->c.stream));
+        ctx->c.prof.reset();
+        ctx->c.prof.on = on != 0;
+        ctx->c.prof.only = -1;
+        return GSC_OK;
+    });
+}
+
+gsc_status gsc_profile_select(gsc_ctx *ctx, const char *kernel) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr, "ctx must not be NULL");
+        if (kernel == nullptr) { ctx->c.prof.only = -1; return GSC_OK; }
+        for (int i = 0; i < KP_COUNT; ++i)
+            if (std::strcmp(kernel, kernel_name(i)) == 0) { ctx->c.prof.only = i; return GSC_OK; }
+        throw Error(GSC_E_ARG, std::string("unknown kernel name: ") + kernel);
+    });
+}
+
+gsc_status gsc_profile_read(gsc_ctx *ctx, const char *kernel, double *total_ms, long long *launches,
+                            double *bytes) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr && kernel != nullptr, "ctx/kernel must not be NULL");
+        {
+            DeviceGuard g(ctx->c.device);
+            GSC_HIP(hipStreamSynchronize(ctx->c.stream));
+            ctx->c.prof.resolve();
+        }
+        for (int i = 0; i < KP_COUNT; ++i) {
+            if (std::strcmp(kernel, kernel_name(i)) == 0) {
+                const auto &a = ctx->c.prof.acc[i];
+                if (total_ms) *total_ms = a.ms;
+                if (launches) *launches = a.launches;
+                if (bytes) *bytes = a.bytes;
+                return GSC_OK;
+            }
+        }
+        throw Error(GSC_E_ARG, std::string("unknown kernel name: ") + kernel);
+    });
 }
 
 gsc_status gsc_solve_batched(gsc_ctx *ctx, int nsys, const gsc_problem *problems, const gsc_opts *opts) {

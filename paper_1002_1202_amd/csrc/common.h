@@ -90,11 +90,47 @@ template <typename T> struct DevBuf {
     T *get() const { return ptr; }
 };
 
+// ------------------------------------------------------------------ kernel timing
+enum KernelId : int {
+    KP_SPMM_SEED = 0, KP_SPMM_S, KP_SHIFT_UPDATE, KP_CG_UPDATE, KP_CG_DIR, KP_UPDATE_R,
+    KP_RHO_DOT, KP_P_UPDATE, KP_CTRL, KP_POST, KP_PROJ_UPDATE, KP_CHEB, KP_COUNT
+};
+const char *kernel_name(int id);
+
+// Events recorded around launches while enabled; resolved at sync points.
+struct Profiler {
+    bool on = false;
+    int only = -1;      // time only this kernel id (-1: all)
+    struct Acc { double ms = 0; long long launches = 0; double bytes = 0; };
+    Acc acc[KP_COUNT];
+    struct Pending { int id; hipEvent_t a, b; double bytes; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get_event();
+    void begin(hipStream_t st, int id, double bytes);
+    void end(hipStream_t st);
+    void resolve();     // call after the stream was synchronised
+    void add_bytes(int id, double bytes) { acc[id].bytes += bytes; }
+    void reset();
+    ~Profiler();
+    bool open_ = false;
+};
+
 // ------------------------------------------------------------------ handles
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int num_cu = 256;
+    Profiler prof;
+};
+
+// Clusters of C consecutive block rows that share one sorted union of their
+// column blocks: ptr[c]..ptr[c+1] index the union (col), blk[u*C + i] is the
+// stored block of (row c*C + i, col[u]) or -1.
+struct Clusters {
+    int C = 0;
+    int nc = 0;
+    DevBuf<int32_t> ptr, col, blk;
 };
 
 struct Pair {
@@ -105,6 +141,7 @@ struct Pair {
     DevBuf<int32_t> colidx;     // nnzb
     DevBuf<int32_t> brow;       // nnzb: block row of every stored block
     DevBuf<int32_t> mirror;     // nnzb: index of the stored block (J, I)
+    Clusters cl;                // register-blocked product layout
     DevBuf<double> H, S;        // nnzb*B*B, FP64
     DevBuf<float> H32, S32;     // FP32 copies for mixed precision products
     bool f32_valid = false;

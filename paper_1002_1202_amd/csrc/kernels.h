@@ -16,6 +16,7 @@
 namespace gsc {
 
 constexpr int kMaxFuse = 16;          // largest m of the fused shift update
+constexpr int kHist = 64;             // CG coefficients kept per column for Ritz bounds
 constexpr int kFrozenNever = 0x7fffffff;
 
 enum : int { FLAG_BREAKDOWN = 1, FLAG_NOT_SPD = 2, FLAG_NAN = 4, FLAG_INNER = 8 };
@@ -28,6 +29,10 @@ struct ColState {
     int *inner_count;
     long long *shift_iters;
     int *iters;
+    long long *inner_total;   // inner CG steps summed over the solve
+    long long *act_hist;      // [max_iter] active (shift, column) pairs per iteration
+    long long *col_hist;      // [max_iter] unfinished columns per iteration
+    double *cg_ha, *cg_hb;    // [Rp][kHist] CG step sizes and beta of a recorded solve (or null)
 };
 
 // (shift, column) state.
@@ -46,6 +51,7 @@ struct TileDims {
     int Lr;                   // rows per group (vector kernels)
     int Gs;                   // row groups of the SpMM kernels (multiple of 8)
     int Lb;                   // block rows per SpMM group
+    int variant = 1;          // SpMM kernel: 0 one block row per wave, 1 register-blocked clusters
 };
 
 // XCD-aware remap of the linear block id: blocks l = x + gx*y are dispatched
@@ -62,5 +68,20 @@ __device__ inline void xcd_remap(int &cx, int &gy) {
 }
 
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Algorithmic-byte counter of a launch (profiling only; ctr may be null):
+// each wave adds (active lanes) x per_lane bytes.
+__device__ inline void count_bytes(unsigned long long *ctr, bool active, unsigned long long per_lane) {
+    if (ctr == nullptr) return;
+    const unsigned long long mask = __ballot(active);
+    if ((threadIdx.x & 63) == 0 && mask != 0ull)
+        atomicAdd(ctr, static_cast<unsigned long long>(__popcll(mask)) * per_lane);
+}
+
+// rows handled by wave w of a row group [i0, i1) (waves interleave rows)
+__device__ inline int wave_rows(int i0, int i1, int w) {
+    const int n = i1 - i0 - w;
+    return n > 0 ? (n + kWavesPerBlock - 1) / kWavesPerBlock : 0;
+}
 
 }  // namespace gsc

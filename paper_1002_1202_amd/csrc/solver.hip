@@ -15,6 +15,7 @@
 // All scalar recurrences, dots and reductions are FP64; vectors and products
 // are complex<T> (T = double, or float in the mixed mode).
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -78,6 +79,7 @@ __global__ void k_init_cols(int R, int Rp, int seed0, ColState cs) {
     cs.sw[c] = 0;
     cs.shift_iters[c] = 0;
     cs.iters[c] = 0;
+    cs.inner_total[c] = 0;
     cs.zres[c] = 0;
     cs.inner_done[c] = 1;
     cs.inner_count[c] = 0;
@@ -168,6 +170,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(int Rp, int G, const double *pa
         return;
     }
     cs.cg_a[c] = cs.rr[c] / dw;
+    if (cs.cg_ha != nullptr && cs.inner_count[c] < kHist)
+        cs.cg_ha[static_cast<size_t>(c) * kHist + cs.inner_count[c]] = cs.cg_a[c];
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_b(int Rp, int G, const double *partial, int inner_max,
@@ -181,8 +185,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(int Rp, int G, const double *pa
     if (threadIdx.x != 0) return;
     const double rr = cs.rr[c];
     cs.cg_b[c] = rr_new / rr;
+    if (cs.cg_hb != nullptr && cs.inner_count[c] < kHist)
+        cs.cg_hb[static_cast<size_t>(c) * kHist + cs.inner_count[c]] = cs.cg_b[c];
     cs.rr[c] = rr_new;
     cs.cg_first[c] = 0;
+    cs.inner_total[c] += 1;
     const int cnt = ++cs.inner_count[c];
     if (!isfinite(rr_new)) {
         cs.flags[c] |= FLAG_NAN;
@@ -197,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(int Rp, int G, const double *pa
 }
 
 // alpha = rho / (p^T A_s p) and the shift coefficients of step n (slot).
-__global__ __launch_bounds__(kBlock) void k_ctrl(int K, int Rp, int G, int slot, const c128 *partial,
+__global__ __launch_bounds__(kBlock) void k_ctrl(int K, int Rp, int G, int n, int slot, const c128 *partial,
                                                  ColState cs, ShiftState ss) {
     __shared__ c128 lds[kBlock];
     __shared__ c128 s_alpha, s_tail, s_zs;
@@ -255,6 +262,11 @@ __global__ __launch_bounds__(kBlock) void k_ctrl(int K, int Rp, int G, int slot,
     if (threadIdx.x == 0) {
         cs.shift_iters[c] += s_cnt[0];
         cs.iters[c] += 1;
+        if (cs.act_hist != nullptr) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(cs.act_hist + n),
+                      static_cast<unsigned long long>(s_cnt[0]));
+            atomicAdd(reinterpret_cast<unsigned long long *>(cs.col_hist + n), 1ull);
+        }
     }
 }
 
@@ -387,6 +399,96 @@ __global__ void k_init_rho(int Rp, int G, const c128 *partial, ColState cs) {
     }
 }
 
+// Extreme Ritz values of the Lanczos tridiagonal that a recorded CG solve
+// (step sizes a_j, ratios b_j) builds implicitly:
+//   T_00 = 1/a_0,  T_jj = 1/a_j + b_{j-1}/a_{j-1},  T_{j,j+1} = sqrt(b_j)/a_j,
+// found by bisection on the Sturm count.  One thread per column.
+__device__ inline int sturm_below(const double *dg, const double *of, int k, double x) {
+    int cnt = 0;
+    double q = dg[0] - x;
+    if (q < 0) ++cnt;
+    for (int j = 1; j < k; ++j) {
+        const double qq = (q == 0.0) ? 1e-300 : q;
+        q = (dg[j] - x) - of[j - 1] * of[j - 1] / qq;
+        if (q < 0) ++cnt;
+    }
+    return cnt;
+}
+
+__global__ void k_ritz(int R, int Rp, ColState cs, double *lmin, double *lmax) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= Rp) return;
+    lmin[c] = 1e300;
+    lmax[c] = -1e300;
+    if (c >= R || cs.zres[c] || cs.done[c]) return;
+    const int k = min(cs.inner_count[c], kHist);
+    if (k < 1) return;
+    double dg[kHist], of[kHist];
+    const double *a = cs.cg_ha + static_cast<size_t>(c) * kHist;
+    const double *b = cs.cg_hb + static_cast<size_t>(c) * kHist;
+    for (int j = 0; j < k; ++j) {
+        dg[j] = 1.0 / a[j] + (j > 0 ? b[j - 1] / a[j - 1] : 0.0);
+        of[j] = j + 1 < k ? sqrt(b[j]) / a[j] : 0.0;
+    }
+    double lo = 1e300, hi = -1e300;
+    for (int j = 0; j < k; ++j) {
+        const double rad = (j > 0 ? fabs(of[j - 1]) : 0.0) + (j + 1 < k ? fabs(of[j]) : 0.0);
+        lo = fmin(lo, dg[j] - rad);
+        hi = fmax(hi, dg[j] + rad);
+    }
+    // smallest eigenvalue: largest x with no eigenvalue below it
+    double x0 = lo, x1 = hi;
+    for (int it = 0; it < 100; ++it) {
+        const double m = 0.5 * (x0 + x1);
+        if (sturm_below(dg, of, k, m) >= 1) x1 = m; else x0 = m;
+    }
+    lmin[c] = x0;
+    x0 = lo; x1 = hi;
+    for (int it = 0; it < 100; ++it) {
+        const double m = 0.5 * (x0 + x1);
+        if (sturm_below(dg, of, k, m) >= k) x1 = m; else x0 = m;
+    }
+    lmax[c] = x1;
+}
+
+__global__ void k_ritz_reduce(int Rp, const double *lmin, const double *lmax, double *out) {
+    __shared__ double a[kBlock], b[kBlock];
+    double mn = 1e300, mx = -1e300;
+    for (int c = threadIdx.x; c < Rp; c += kBlock) { mn = fmin(mn, lmin[c]); mx = fmax(mx, lmax[c]); }
+    a[threadIdx.x] = mn;
+    b[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            a[threadIdx.x] = fmin(a[threadIdx.x], a[threadIdx.x + s]);
+            b[threadIdx.x] = fmax(b[threadIdx.x], b[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = a[0]; out[1] = b[0]; }
+}
+
+// Residual check of the Chebyshev iteration: a column is finished when
+// ||r - S y|| <= thr * ||r|| (inner_done = 1), else it needs more steps.
+__global__ __launch_bounds__(kBlock) void k_cheb_check(int Rp, int G, const double *partial, double thr,
+                                                       ColState cs) {
+    __shared__ double lds[kBlock];
+    const int c = blockIdx.x;
+    if (cs.done[c] || cs.inner_done[c]) return;
+    double v = 0.0;
+    for (int g = threadIdx.x; g < G; g += kBlock) v += partial[static_cast<size_t>(g) * Rp + c];
+    const double rr = block_sum(v, lds);
+    if (threadIdx.x != 0) return;
+    if (!isfinite(rr)) { cs.flags[c] |= FLAG_NAN; cs.done[c] = 1; cs.inner_done[c] = 1; return; }
+    if (rr <= thr * thr * cs.rnorm2[c]) cs.inner_done[c] = 1;
+}
+
+template <typename T>
+__global__ void k_copy_vec(size_t n, const cpx<T> *a, cpx<T> *b) {
+    const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
 __global__ void k_status(int Rp, ColState cs, Status *st) {
     __shared__ int a[kBlock], b[kBlock], s[kBlock], f[kBlock];
     int na = 0, nb = 0, ns = 0, fl = 0;
@@ -420,7 +522,8 @@ __global__ void k_status(int Rp, ColState cs, Status *st) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_r(int N, int Rp, int Lr, const int *done,
                                                      const c128 *alpha, const cpx<T> *q, cpx<T> *r,
-                                                     cpx<T> *res, cpx<T> *d, double *partial) {
+                                                     cpx<T> *res, cpx<T> *d, double *partial,
+                                                     unsigned long long *ctr) {
     ELEM_LOOP_BEGIN
     double acc = 0.0;
     if (!done[col]) {
@@ -441,7 +544,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_update(int N, int Rp, int Lr, const int *inner_done,
                                                       const int *first, const double *cg_a,
                                                       const cpx<T> *d, const cpx<T> *w, cpx<T> *y,
-                                                      cpx<T> *res, double *partial) {
+                                                      cpx<T> *res, double *partial, unsigned long long *ctr) {
     ELEM_LOOP_BEGIN
     double acc = 0.0;
     if (!inner_done[col]) {
@@ -462,7 +565,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int N, int Rp, int Lr, con
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_dir(int N, int Rp, int Lr, const int *inner_done,
-                                                   const double *cg_b, const cpx<T> *res, cpx<T> *d) {
+                                                   const double *cg_b, const cpx<T> *res, cpx<T> *d,
+                                                   unsigned long long *ctr) {
     ELEM_LOOP_BEGIN
     if (inner_done[col]) return;
     const T b = static_cast<T>(cg_b[col]);
@@ -475,7 +579,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(int N, int Rp, int Lr, const 
 // partial r'^T r (unconjugated)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rho_dot(int N, int Rp, int Lr, const int *done, const int *zres,
-                                                    const cpx<T> *rp, const cpx<T> *r, c128 *partial) {
+                                                    const cpx<T> *rp, const cpx<T> *r, c128 *partial,
+                                                    unsigned long long *ctr) {
     ELEM_LOOP_BEGIN
     c128 acc{0, 0};
     if (!done[col] && !zres[col]) {
@@ -492,7 +597,7 @@ __global__ __launch_bounds__(kBlock) void k_rho_dot(int N, int Rp, int Lr, const
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_p_update(int N, int Rp, int Lr, int init, ColState cs,
                                                      cpx<T> *rp, cpx<T> *r, cpx<T> *p, const cpx<T> *P,
-                                                     size_t ldk) {
+                                                     size_t ldk, unsigned long long *ctr) {
     ELEM_LOOP_BEGIN
     if (cs.done[col]) return;
     const int sw = init ? 2 : cs.sw[col];
@@ -532,11 +637,12 @@ __global__ void k_mark_applied(int Rp, int n1, ColState cs) {
 // recurrences to x^k, p^k of column c:  p <- a_t r'_t + b_t p;  x <- x + c_t p,
 // skipping steps after a shift froze.  r'_t stays in registers across all
 // shifts of the block; x^k, p^k are read and written once per pass.
-template <typename T, int M, int E>
+template <typename T, int M, int E, int KU>
 __global__ __launch_bounds__(kBlock) void k_flush(int N, int Rp, int K, int m, int n0, int n1, int only_sw,
                                                   int kper, ColState cs, ShiftState ss,
-                                                  const cpx<T> *ring, size_t ring_ld, cpx<T> *X, size_t ldx,
-                                                  cpx<T> *P, size_t ldp) {
+                                                  const cpx<T> *__restrict__ ring, size_t ring_ld,
+                                                  cpx<T> *__restrict__ X, size_t ldx, cpx<T> *__restrict__ P,
+                                                  size_t ldp) {
     const int col = blockIdx.y;
     if (only_sw && cs.sw[col] != 1) return;
     const int tb = max(n0, cs.applied[col]);
@@ -557,37 +663,53 @@ __global__ __launch_bounds__(kBlock) void k_flush(int N, int Rp, int K, int m, i
     const size_t KR = static_cast<size_t>(K) * Rp;
     const int k0 = blockIdx.z * kper;
     const int k1 = min(K, k0 + kper);
-    for (int k = k0; k < k1; ++k) {
-        const size_t idx = static_cast<size_t>(k) * Rp + col;
-        const int last = ss.last[idx];
-        const int kend = last >= n1 ? n1 : last + 1;
-        const int kc = kend - tb;
-        if (kc <= 0) continue;
-        cpx<T> *Xk = X + static_cast<size_t>(k) * ldx + static_cast<size_t>(col) * N;
-        cpx<T> *Pk = P + static_cast<size_t>(k) * ldp + static_cast<size_t>(col) * N;
-        cpx<T> pv[E], xv[E];
+    for (int k = k0; k < k1; k += KU) {
+        // KU shifts in flight: loads of all of them are issued before the math
+        int kc[KU];
+        cpx<T> pv[KU][E], xv[KU][E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int i = ibase + e * kBlock;
-            pv[e] = i < N ? Pk[i] : cpx<T>{0, 0};
-            xv[e] = i < N ? Xk[i] : cpx<T>{0, 0};
+        for (int u = 0; u < KU; ++u) {
+            kc[u] = 0;
+            if (k + u < k1) {
+                const int last = ss.last[static_cast<size_t>(k + u) * Rp + col];
+                kc[u] = (last >= n1 ? n1 : last + 1) - tb;
+            }
+            const size_t base = static_cast<size_t>(col) * N;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int i = ibase + e * kBlock;
+                const bool ok = kc[u] > 0 && i < N;
+                pv[u][e] = ok ? P[static_cast<size_t>(k + u) * ldp + base + i] : cpx<T>{0, 0};
+                xv[u][e] = ok ? X[static_cast<size_t>(k + u) * ldx + base + i] : cpx<T>{0, 0};
+            }
         }
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            if (j < kc) {
-                const size_t s = static_cast<size_t>((tb + j) % m) * KR + idx;
-                const cpx<T> a = ccast<T>(ss.ra[s]), b = ccast<T>(ss.rb[s]), cc = ccast<T>(ss.rc[s]);
 #pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    pv[e] = a * rr[j][e] + b * pv[e];
-                    xv[e] = xv[e] + cc * pv[e];
+            for (int u = 0; u < KU; ++u) {
+                if (j < kc[u]) {
+                    const size_t sidx = static_cast<size_t>((tb + j) % m) * KR + static_cast<size_t>(k + u) * Rp + col;
+                    const cpx<T> a = ccast<T>(ss.ra[sidx]), b = ccast<T>(ss.rb[sidx]), cc = ccast<T>(ss.rc[sidx]);
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        pv[u][e] = a * rr[j][e] + b * pv[u][e];
+                        xv[u][e] = xv[u][e] + cc * pv[u][e];
+                    }
                 }
             }
         }
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int i = ibase + e * kBlock;
-            if (i < N) { Pk[i] = pv[e]; Xk[i] = xv[e]; }
+        for (int u = 0; u < KU; ++u) {
+            if (kc[u] <= 0) continue;
+            const size_t base = static_cast<size_t>(col) * N;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int i = ibase + e * kBlock;
+                if (i < N) {
+                    P[static_cast<size_t>(k + u) * ldp + base + i] = pv[u][e];
+                    X[static_cast<size_t>(k + u) * ldx + base + i] = xv[u][e];
+                }
+            }
         }
     }
 }
@@ -741,7 +863,8 @@ template <typename T> struct Tile {
     DevBuf<double> c_bnorm, c_rnorm2, c_rr, c_rr_stop, c_cg_a, c_cg_b;
     DevBuf<int> c_seed, c_done, c_inner_done, c_cg_first, c_sw, c_applied, c_flags, c_zres, c_inner_count,
         c_iters;
-    DevBuf<long long> c_shift_iters;
+    DevBuf<long long> c_shift_iters, c_inner_total, act_hist, col_hist;
+    DevBuf<double> cg_ha, cg_hb;
     // shift state
     DevBuf<c128> s_pi, s_pi_prev, s_pi_next, s_omega, s_ra, s_rb, s_rc;
     DevBuf<double> s_res;
@@ -763,6 +886,8 @@ template <typename T> struct Tile {
         c.inner_done = c_inner_done.get(); c.cg_first = c_cg_first.get(); c.sw = c_sw.get();
         c.applied = c_applied.get(); c.flags = c_flags.get(); c.zres = c_zres.get();
         c.inner_count = c_inner_count.get(); c.shift_iters = c_shift_iters.get(); c.iters = c_iters.get();
+        c.inner_total = c_inner_total.get(); c.act_hist = act_hist.get(); c.col_hist = col_hist.get();
+        c.cg_ha = cg_ha.get(); c.cg_hb = cg_hb.get();
         return c;
     }
     ShiftState shifts(const c128 *z) {
@@ -801,9 +926,15 @@ template <typename T> class TileSolver {
         td.m = m;
         td.G = pick_groups(td.N, Rp / 64, 2048);
         td.Lr = div_up(td.N, td.G);
-        td.Gs = pick_groups(td.nb, Rp / 64, 2048);
-        td.Lb = div_up(td.nb, td.Gs);
+        set_spmm_geometry(td, pr_, req.opts.spmm_kernel == 2 ? 1 : 0);
         st_ = ctx_.stream;
+        if (ctx_.prof.on) {
+            const int mi = std::max(1, req.opts.max_iter);
+            t_.act_hist.alloc(mi);
+            t_.col_hist.alloc(mi);
+            GSC_HIP(hipMemsetAsync(t_.act_hist.get(), 0, mi * sizeof(long long), st_));
+            GSC_HIP(hipMemsetAsync(t_.col_hist.get(), 0, mi * sizeof(long long), st_));
+        }
     }
 
     void allocate() {
@@ -819,6 +950,9 @@ template <typename T> class TileSolver {
         t_.c_seed.alloc(Rp); t_.c_done.alloc(Rp); t_.c_inner_done.alloc(Rp); t_.c_cg_first.alloc(Rp);
         t_.c_sw.alloc(Rp); t_.c_applied.alloc(Rp); t_.c_flags.alloc(Rp); t_.c_zres.alloc(Rp);
         t_.c_inner_count.alloc(Rp); t_.c_iters.alloc(Rp); t_.c_shift_iters.alloc(Rp);
+        t_.c_inner_total.alloc(Rp);
+        t_.cg_ha.alloc(Rp * kHist);
+        t_.cg_hb.alloc(Rp * kHist);
         const size_t KR = static_cast<size_t>(td.K) * Rp;
         t_.s_pi.alloc(KR); t_.s_pi_prev.alloc(KR); t_.s_pi_next.alloc(KR); t_.s_omega.alloc(KR);
         t_.s_res.alloc(KR); t_.s_last.alloc(KR);
@@ -884,12 +1018,14 @@ template <typename T> class TileSolver {
         k_init_rhs<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, td.R, drhs_, dB_, t_.r.get(), t_.res.get(),
                                          t_.d.get(), t_.part_d.get());
         k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 1, inner_tol, cs);
-        inner_solve(o, cs, t_.ring.get());
+        inner_tol_ = inner_tol;
+        inner_solve_cg(o, cs, t_.ring.get());
+        if (o.inner_method != 1) setup_chebyshev(o, inner_tol);
         k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), t_.ring.get(),
-                                        t_.r.get(), t_.part_c.get());
+                                        t_.r.get(), t_.part_c.get(), nullptr);
         k_init_rho<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_c.get(), cs);
         k_p_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, 1, cs, t_.ring.get(), t_.r.get(), t_.p.get(),
-                                         t_.P.get(), t_.ldk);
+                                         t_.P.get(), t_.ldk, nullptr);
         GSC_HIP(hipGetLastError());
         check_status(false);
 
@@ -900,9 +1036,13 @@ template <typename T> class TileSolver {
             const int slot = n % td.m, slot_next = (n + 1) % td.m;
             cpx<T> *rp_n = t_.ring.get() + slot * NR;
             cpx<T> *rp_next = t_.ring.get() + slot_next * NR;
+            prof_.begin(st_, KP_SPMM_SEED, 2.0 * mat_bytes());
             launch_spmm_seed<T>(st_, pr_, td, Sv, Hv, t_.p.get(), t_.q.get(), dz_, t_.c_seed.get(),
-                                t_.c_done.get(), t_.part_c.get());
-            k_ctrl<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.Gs, slot, t_.part_c.get(), cs, ss);
+                                t_.c_done.get(), t_.part_c.get(), ctr(KP_SPMM_SEED));
+            prof_.end(st_);
+            prof_.begin(st_, KP_CTRL, 0.0);
+            k_ctrl<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.Gs, n, slot, t_.part_c.get(), cs, ss);
+            prof_.end(st_);
             if (full_) {
                 if (n + 1 - n0 == td.m) {
                     flush(cs, ss, n0, n + 1, 0);
@@ -911,26 +1051,36 @@ template <typename T> class TileSolver {
             } else {
                 proj_update(cs, ss, slot, rp_n);
             }
+            prof_.begin(st_, KP_UPDATE_R, 0.0);
             k_update_r<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_alpha.get(),
-                                             t_.q.get(), t_.r.get(), t_.res.get(), t_.d.get(), t_.part_d.get());
+                                             t_.q.get(), t_.r.get(), t_.res.get(), t_.d.get(), t_.part_d.get(),
+                                             ctr(KP_UPDATE_R));
+            prof_.end(st_);
             k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 0, inner_tol, cs);
             inner_solve(o, cs, rp_next);
+            prof_.begin(st_, KP_RHO_DOT, 0.0);
             k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), rp_next,
-                                            t_.r.get(), t_.part_c.get());
+                                            t_.r.get(), t_.part_c.get(), ctr(KP_RHO_DOT));
+            prof_.end(st_);
+            prof_.begin(st_, KP_POST, 0.0);
             k_post<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.G, n, full_ ? 1 : 0, t_.part_c.get(), o.tol, cs,
                                               ss, t_.h.get(), t_.Mu + t_.srow);
+            prof_.end(st_);
             GSC_HIP(hipGetLastError());
             const Status s = check_status(true);
             if (full_ && s.switched > 0) {
-                flush(cs, ss, n0, n + 1, 1);
+                flush(cs, ss, n0, n + 1, 1, s.switched);
                 k_mark_applied<<<cb, 256, 0, st_>>>(td.Rp, n + 1, cs);
             }
+            prof_.begin(st_, KP_P_UPDATE, 0.0);
             k_p_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, 0, cs, rp_next, t_.r.get(), t_.p.get(),
-                                             t_.P.get(), t_.ldk);
+                                             t_.P.get(), t_.ldk, ctr(KP_P_UPDATE));
+            prof_.end(st_);
             if (s.active_cols == 0) { ++n; break; }
         }
         if (full_ && n > n0) flush(cs, ss, n0, n, 0);
         GSC_HIP(hipGetLastError());
+        if (prof_.on) account_bytes(n);
         return n;
     }
 
@@ -1047,6 +1197,52 @@ template <typename T> class TileSolver {
   private:
     const T *sval() const;
     const T *hval() const;
+    unsigned long long *ctr(int) { return nullptr; }
+
+    // Algorithmic bytes of every kernel class over this solve (the method's
+    // own reads and writes of N-long vectors; gathers and re-reads excluded),
+    // from per-column iteration counters and the per-iteration active counts.
+    void account_bytes(int n_iters) {
+        auto &td = t_.td;
+        std::vector<int> it(td.Rp);
+        std::vector<long long> inner(td.Rp), act(std::max(1, n_iters)), cols(std::max(1, n_iters));
+        GSC_HIP(hipMemcpyAsync(it.data(), t_.c_iters.get(), td.Rp * sizeof(int), hipMemcpyDeviceToHost, st_));
+        GSC_HIP(hipMemcpyAsync(inner.data(), t_.c_inner_total.get(), td.Rp * sizeof(long long),
+                               hipMemcpyDeviceToHost, st_));
+        if (n_iters > 0) {
+            GSC_HIP(hipMemcpyAsync(act.data(), t_.act_hist.get(), n_iters * sizeof(long long),
+                                   hipMemcpyDeviceToHost, st_));
+            GSC_HIP(hipMemcpyAsync(cols.data(), t_.col_hist.get(), n_iters * sizeof(long long),
+                                   hipMemcpyDeviceToHost, st_));
+        }
+        GSC_HIP(hipStreamSynchronize(st_));
+        double s_it = 0, s_in = 0;
+        for (int c = 0; c < td.R; ++c) { s_it += it[c]; s_in += inner[c]; }
+        const double solves = s_it + td.R;
+        const double vec = static_cast<double>(td.N) * sizeof(cpx<T>);
+        prof_.add_bytes(KP_SPMM_SEED, s_it * vec * 2);
+        prof_.add_bytes(KP_UPDATE_R, s_it * vec * 5);
+        prof_.add_bytes(KP_RHO_DOT, solves * vec * 2);
+        prof_.add_bytes(KP_P_UPDATE, solves * vec * 3);
+        prof_.add_bytes(KP_SPMM_S, s_in * vec * 2);
+        prof_.add_bytes(KP_CG_UPDATE, (6 * s_in - solves) * vec);
+        prof_.add_bytes(KP_CG_DIR, 3 * (s_in - solves) * vec);
+        double fb = 0;
+        for (const auto &f : flushes_) {
+            const int n0 = f[0], n1 = f[1], nsw = f[2];
+            if (n0 >= n_iters) continue;
+            const double a = static_cast<double>(act[n0]), cc = static_cast<double>(cols[n0]);
+            if (nsw < 0) {
+                fb += (4.0 * a + cc * (n1 - n0)) * vec;        // full pass over every active (k, c)
+            } else if (cc > 0) {
+                fb += nsw * (4.0 * a / cc + (n1 - n0)) * vec;  // seed-switch columns only
+            }
+        }
+        prof_.add_bytes(KP_SHIFT_UPDATE, fb);
+        prof_.resolve();
+    }
+    std::vector<std::array<int, 3>> flushes_;
+    double mat_bytes() const { return static_cast<double>(pr_.nnzb) * pr_.B * pr_.B * sizeof(T); }
 
     Status check_status(bool count_switch) {
         auto &td = t_.td;
@@ -1056,6 +1252,7 @@ template <typename T> class TileSolver {
         GSC_HIP(hipStreamSynchronize(st_));
         const Status s = *hs_.h;
         flags_ |= s.flags;
+        last_active_ = s.active_cols;
         if (count_switch) switches_ += s.switched;
         if (s.flags & FLAG_NAN) throw Error(GSC_E_NAN, "non-finite value in the iteration");
         if (s.flags & FLAG_NOT_SPD) throw Error(GSC_E_S_NOT_SPD, "inner CG found d^H S d <= 0: S is not positive definite");
@@ -1064,6 +1261,83 @@ template <typename T> class TileSolver {
     }
 
     void inner_solve(const gsc_opts &o, ColState cs, cpx<T> *y) {
+        if (cheb_ok_) inner_solve_cheb(o, cs, y);
+        else inner_solve_cg(o, cs, y);
+    }
+
+    // Interval for the Chebyshev iteration from the Ritz values of the first
+    // (CG) inner solve over all columns, widened by 10 % of its width.
+    void setup_chebyshev(const gsc_opts &o, double tol_in) {
+        auto &td = t_.td;
+        DevBuf<double> lmin(td.Rp), lmax(td.Rp), out(2);
+        ColState cs = t_.cols();
+        k_ritz<<<div_up(td.Rp, 64), 64, 0, st_>>>(td.R, td.Rp, cs, lmin.get(), lmax.get());
+        k_ritz_reduce<<<1, kBlock, 0, st_>>>(td.Rp, lmin.get(), lmax.get(), out.get());
+        GSC_HIP(hipGetLastError());
+        double h[2];
+        GSC_HIP(hipMemcpyAsync(h, out.get(), sizeof(h), hipMemcpyDeviceToHost, st_));
+        GSC_HIP(hipStreamSynchronize(st_));
+        cheb_ok_ = false;
+        if (!(h[0] < 1e299 && h[1] > -1e299)) return;
+        const double w = h[1] - h[0];
+        const double pad = std::max(0.1 * w, 1e-3 * std::fabs(h[1]));
+        const double a = h[0] - pad, b = h[1] + pad;
+        if (!(a > 0.0) || !std::isfinite(b)) return;
+        cheb_theta_ = 0.5 * (b + a);
+        cheb_delta_ = 0.5 * (b - a);
+        const double kappa = b / a;
+        cheb_rho_ = (std::sqrt(kappa) - 1.0) / (std::sqrt(kappa) + 1.0);
+        const double lr = std::log(1.0 / std::max(cheb_rho_, 1e-300));
+        cheb_steps_ = std::max(2, static_cast<int>(std::ceil(std::log(2.0 / tol_in) / lr)));
+        cheb_steps_ = std::min(cheb_steps_, o.inner_max_iter);
+        cheb_ok_ = true;
+        cheb_lo_ = h[0];
+        cheb_hi_ = h[1];
+    }
+
+    // Chebyshev iteration for S y = r (r in t_.r), y_K written to `ytarget`.
+    void inner_solve_cheb(const gsc_opts &o, ColState cs, cpx<T> *ytarget) {
+        auto &td = t_.td;
+        const T *Sv = sval();
+        const double sigma = cheb_theta_ / cheb_delta_;
+        const int K = cheb_steps_;
+        cpx<T> *buf[2];
+        buf[K % 2] = ytarget;
+        buf[(K + 1) % 2] = t_.w.get();
+        double rho_prev = 1.0 / sigma;
+        int k = 1;
+        auto step = [&](int kk) {
+            const double rho = 1.0 / (2.0 * sigma - rho_prev);
+            const double c1 = rho * rho_prev, c2 = 2.0 * rho / cheb_delta_;
+            prof_.begin(st_, KP_CHEB, static_cast<double>(last_active_) * td.N * sizeof(cpx<T>) * (kk == 1 ? 3 : 5));
+            launch_cheb_step<T>(st_, pr_, td, kk == 1, Sv, buf[kk % 2], t_.r.get(), t_.d.get(),
+                                buf[(kk + 1) % 2], t_.c_done.get(), 1.0 / cheb_theta_, c1, c2, t_.part_d.get());
+            prof_.end(st_);
+            rho_prev = rho;
+        };
+        for (; k < K; ++k) step(k);
+        // residual of y_{K-1} (one step behind y_K): accept at tol / rho
+        k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_ / cheb_rho_, cs);
+        GSC_HIP(hipGetLastError());
+        Status s = check_status(false);
+        int extra = 0;
+        while (s.inner_pending > 0 && K + extra < o.inner_max_iter) {
+            step(k);
+            ++k;
+            ++extra;
+            k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_, cs);
+            s = check_status(false);
+        }
+        if (k % 2 != K % 2) {
+            const size_t n = static_cast<size_t>(td.N) * td.Rp;
+            k_copy_vec<T><<<div_up(static_cast<int64_t>(n), 256), 256, 0, st_>>>(n, buf[k % 2], ytarget);
+            GSC_HIP(hipGetLastError());
+        }
+        cheb_extra_ += extra;
+        inner_total_ += k - 1;
+    }
+
+    void inner_solve_cg(const gsc_opts &o, ColState cs, cpx<T> *y) {
         auto &td = t_.td;
         const dim3 eg(td.Rp / 64, td.G), eb(kBlock);
         int done_steps = 0;
@@ -1071,14 +1345,21 @@ template <typename T> class TileSolver {
         const T *Sv = sval();
         while (true) {
             for (int j = 0; j < chunk; ++j) {
-                launch_spmm_S<T>(st_, pr_, td, Sv, t_.d.get(), t_.w.get(), t_.c_inner_done.get(), t_.part_d.get());
+                prof_.begin(st_, KP_SPMM_S, mat_bytes());
+                launch_spmm_S<T>(st_, pr_, td, Sv, t_.d.get(), t_.w.get(), t_.c_inner_done.get(), t_.part_d.get(),
+                                 ctr(KP_SPMM_S));
+                prof_.end(st_);
                 k_cg_a<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), cs);
+                prof_.begin(st_, KP_CG_UPDATE, 0.0);
                 k_cg_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_inner_done.get(), t_.c_cg_first.get(),
                                                   t_.c_cg_a.get(), t_.d.get(), t_.w.get(), y, t_.res.get(),
-                                                  t_.part_d.get());
+                                                  t_.part_d.get(), ctr(KP_CG_UPDATE));
+                prof_.end(st_);
                 k_cg_b<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), o.inner_max_iter, cs);
+                prof_.begin(st_, KP_CG_DIR, 0.0);
                 k_cg_dir<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_inner_done.get(), t_.c_cg_b.get(),
-                                               t_.res.get(), t_.d.get());
+                                               t_.res.get(), t_.d.get(), ctr(KP_CG_DIR));
+                prof_.end(st_);
             }
             GSC_HIP(hipGetLastError());
             done_steps += chunk;
@@ -1090,21 +1371,24 @@ template <typename T> class TileSolver {
         inner_guess_ = std::max(1, done_steps);
     }
 
-    void flush(ColState cs, ShiftState ss, int n0, int n1, int only_sw) {
+    void flush(ColState cs, ShiftState ss, int n0, int n1, int only_sw, int nsw = -1) {
         auto &td = t_.td;
+        if (prof_.on) flushes_.push_back({n0, n1, only_sw ? nsw : -1});
         constexpr int E = 2;
         const int kper = std::max(1, std::min(td.K, 64));
         dim3 grid(div_up(td.N, kBlock * E), td.R, div_up(td.K, kper));
         const size_t NR = static_cast<size_t>(td.N) * td.Rp;
-#define GSC_FLUSH(MM)                                                                                    \
-    k_flush<T, MM, E><<<grid, kBlock, 0, st_>>>(td.N, td.Rp, td.K, td.m, n0, n1, only_sw, kper, cs, ss, \
-                                                t_.ring.get(), NR, t_.X, ldk_x_, t_.P.get(), t_.ldk)
+        prof_.begin(st_, KP_SHIFT_UPDATE, 0.0);
+#define GSC_FLUSH(MM)                                                                                        \
+    k_flush<T, MM, E, 1><<<grid, kBlock, 0, st_>>>(td.N, td.Rp, td.K, td.m, n0, n1, only_sw, kper, cs, ss, \
+                                                   t_.ring.get(), NR, t_.X, ldk_x_, t_.P.get(), t_.ldk)
         if (td.m <= 1) GSC_FLUSH(1);
         else if (td.m <= 2) GSC_FLUSH(2);
         else if (td.m <= 4) GSC_FLUSH(4);
         else if (td.m <= 8) GSC_FLUSH(8);
         else GSC_FLUSH(16);
 #undef GSC_FLUSH
+        prof_.end(st_);
         GSC_HIP(hipGetLastError());
     }
 
@@ -1112,13 +1396,17 @@ template <typename T> class TileSolver {
         auto &td = t_.td;
         const int M = t_.Mu + t_.srow;
         const size_t shm = static_cast<size_t>(M) * sizeof(c128);
+        prof_.begin(st_, KP_PROJ_UPDATE, 0.0);
         k_proj_update<T><<<td.Rp, kBlock, shm, st_>>>(td.K, td.Rp, t_.Mu, t_.srow, slot, td.B, pr_.rowptr.get(),
                                                      pr_.colidx.get(), pr_.S.get(), drhs_, t_.pidx.get(), cs, ss,
                                                      rp, t_.h.get(), t_.gacc.get());
+        prof_.end(st_);
         GSC_HIP(hipGetLastError());
     }
 
     Ctx &ctx_;
+    Profiler &prof_ = ctx_.prof;
+    DevBuf<unsigned long long> ctr_;
     const SolveRequest &req_;
     const Pair &pr_;
     const c128 *dz_;
@@ -1131,6 +1419,12 @@ template <typename T> class TileSolver {
     size_t ldk_x_ = 0;
     HostStatus hs_;
     int inner_guess_ = 8;
+    int last_active_ = 0;
+    double inner_tol_ = 1e-12;
+    bool cheb_ok_ = false;
+    double cheb_theta_ = 1.0, cheb_delta_ = 0.5, cheb_rho_ = 0.5, cheb_lo_ = 0.0, cheb_hi_ = 0.0;
+    int cheb_steps_ = 0;
+    long long cheb_extra_ = 0;
     long long inner_total_ = 0;
     int switches_ = 0;
     long long shift_rhs_iters_ = 0;

@@ -3,13 +3,21 @@
 
 namespace gsc {
 
+// variant 0: one block row per wave; 1: register-blocked clusters
+void set_spmm_geometry(TileDims &td, const Pair &pr, int variant);
+
 template <typename T>
 void launch_spmm_seed(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const T *Hv,
                       const cpx<T> *p, cpx<T> *q, const c128 *z, const int *seed, const int *skip,
-                      c128 *partial);
+                      c128 *partial, unsigned long long *ctr = nullptr);
 
 template <typename T>
 void launch_spmm_S(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const cpx<T> *d,
-                   cpx<T> *w, const int *skip, double *partial);
+                   cpx<T> *w, const int *skip, double *partial, unsigned long long *ctr = nullptr);
+
+template <typename T>
+void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, bool first, const T *Sv,
+                      const cpx<T> *y, const cpx<T> *r, cpx<T> *d, cpx<T> *ynext, const int *skip, double inv_theta,
+                      double c1, double c2, double *partial);
 
 }  // namespace gsc

@@ -6,6 +6,8 @@
 // 1 KiB (FP64) transaction per orbital row).  No MFMA: per stored value the
 // product does 2 (S only) or 4 (S and H) FMAs per complex column against
 // >= 16 bytes of vector traffic, far below the FP64 ridge.
+#include <algorithm>
+
 #include "spmm.h"
 
 namespace gsc {
@@ -18,7 +20,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_seed(
     int nb, int Rp, int Lb, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const T *__restrict__ Sv, const T *__restrict__ Hv, const cpx<T> *__restrict__ p,
     cpx<T> *__restrict__ q, const c128 *__restrict__ z, const int *__restrict__ seed,
-    const int *__restrict__ skip, c128 *__restrict__ partial) {
+    const int *__restrict__ skip, c128 *__restrict__ partial, unsigned long long *ctr) {
     int cx, g;
     xcd_remap(cx, g);
     const int lane = threadIdx.x & 63;
@@ -36,6 +38,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_seed(
 #pragma unroll
             for (int a = 0; a < B; ++a) { aS[a] = {0, 0}; aH[a] = {0, 0}; own[a] = {0, 0}; }
             const int b0 = rowptr[I], b1 = rowptr[I + 1];
+#pragma unroll 2
             for (int b = b0; b < b1; ++b) {
                 const int J = colidx[b];
                 const T *sb = Sv + static_cast<size_t>(b) * B * B;
@@ -87,7 +90,7 @@ template <typename T, int B>
 __global__ __launch_bounds__(kBlock) void k_spmm_S(
     int nb, int Rp, int Lb, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const T *__restrict__ Sv, const cpx<T> *__restrict__ d, cpx<T> *__restrict__ wout,
-    const int *__restrict__ skip, double *__restrict__ partial) {
+    const int *__restrict__ skip, double *__restrict__ partial, unsigned long long *ctr) {
     int cx, g;
     xcd_remap(cx, g);
     const int lane = threadIdx.x & 63;
@@ -103,6 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_S(
 #pragma unroll
             for (int a = 0; a < B; ++a) { aS[a] = {0, 0}; own[a] = {0, 0}; }
             const int b0 = rowptr[I], b1 = rowptr[I + 1];
+#pragma unroll 2
             for (int b = b0; b < b1; ++b) {
                 const int J = colidx[b];
                 const T *sb = Sv + static_cast<size_t>(b) * B * B;
@@ -145,43 +149,348 @@ __global__ __launch_bounds__(kBlock) void k_spmm_S(
     }
 }
 
+// ------------------------------------------------------------------ cluster variants
+// One wave owns 64 columns and a cluster of C consecutive block rows; it
+// walks the sorted union of the cluster's column blocks, loads each x block
+// once and applies it to every row of the cluster that stores that block
+// (register blocking: C*B complex accumulators per lane).
+
+// q = zs_c * (S p) - H p with the complex coefficient (zs s - h) per entry;
+// partial sum_i p_i q_i.
+template <typename T, int B, int C>
+__global__ __launch_bounds__(kBlock) void k_spmm_seed_cl(
+    int nb, int nc, int Rp, int Lc, const int32_t *__restrict__ cptr, const int32_t *__restrict__ ccol,
+    const int32_t *__restrict__ cblk, const T *__restrict__ Sv, const T *__restrict__ Hv,
+    const cpx<T> *__restrict__ p, cpx<T> *__restrict__ q, const c128 *__restrict__ z,
+    const int *__restrict__ seed, const int *__restrict__ skip, c128 *__restrict__ partial) {
+    int cx, g;
+    xcd_remap(cx, g);
+    const int lane = threadIdx.x & 63;
+    const int w = wave_id();
+    const int col = cx * 64 + lane;
+    const bool act = skip == nullptr || !skip[col];
+    const c128 zs = act ? z[seed[col]] : c128{0, 0};
+    const T zr = static_cast<T>(zs.re), zi = static_cast<T>(zs.im);
+    c128 dot{0.0, 0.0};
+    const int c0 = g * Lc;
+    const int c1 = min(nc, c0 + Lc);
+    if (__ballot(act) != 0) {
+        for (int cl = c0 + w; cl < c1; cl += kWavesPerBlock) {
+            cpx<T> acc[C][B];
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+#pragma unroll
+                for (int a = 0; a < B; ++a) acc[i][a] = {0, 0};
+            const int u0 = cptr[cl], u1 = cptr[cl + 1];
+            for (int u = u0; u < u1; ++u) {
+                const int J = ccol[u];
+                cpx<T> x[B];
+#pragma unroll
+                for (int c = 0; c < B; ++c)
+                    x[c] = act ? p[static_cast<size_t>(J * B + c) * Rp + col] : cpx<T>{0, 0};
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    const int b = cblk[u * C + i];
+                    if (b < 0) continue;
+                    const T *sb = Sv + static_cast<size_t>(b) * B * B;
+                    const T *hb = Hv + static_cast<size_t>(b) * B * B;
+#pragma unroll
+                    for (int a = 0; a < B; ++a) {
+#pragma unroll
+                        for (int c = 0; c < B; ++c) {
+                            const T sv = sb[a * B + c], hv = hb[a * B + c];
+                            const T cr = fma(zr, sv, -hv), ci = zi * sv;
+                            acc[i][a].re = fma(cr, x[c].re, fma(-ci, x[c].im, acc[i][a].re));
+                            acc[i][a].im = fma(cr, x[c].im, fma(ci, x[c].re, acc[i][a].im));
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                const int I = cl * C + i;
+                if (I < nb && act) {
+#pragma unroll
+                    for (int a = 0; a < B; ++a) {
+                        const size_t e = static_cast<size_t>(I * B + a) * Rp + col;
+                        q[e] = acc[i][a];
+                        dot = dot + ccast<double>(p[e]) * ccast<double>(acc[i][a]);
+                    }
+                }
+            }
+        }
+    }
+    __shared__ c128 red[kWavesPerBlock][64];
+    red[w][lane] = dot;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        c128 s = red[0][lane];
+#pragma unroll
+        for (int k = 1; k < kWavesPerBlock; ++k) s = s + red[k][lane];
+        partial[static_cast<size_t>(g) * Rp + col] = s;
+    }
+}
+
+// w = S d, partial Re(d^H S d)
+template <typename T, int B, int C>
+__global__ __launch_bounds__(kBlock) void k_spmm_S_cl(
+    int nb, int nc, int Rp, int Lc, const int32_t *__restrict__ cptr, const int32_t *__restrict__ ccol,
+    const int32_t *__restrict__ cblk, const T *__restrict__ Sv, const cpx<T> *__restrict__ d,
+    cpx<T> *__restrict__ wout, const int *__restrict__ skip, double *__restrict__ partial) {
+    int cx, g;
+    xcd_remap(cx, g);
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_id();
+    const int col = cx * 64 + lane;
+    const bool act = !skip[col];
+    double dot = 0.0;
+    const int c0 = g * Lc;
+    const int c1 = min(nc, c0 + Lc);
+    if (__ballot(act) != 0) {
+        for (int cl = c0 + wv; cl < c1; cl += kWavesPerBlock) {
+            cpx<T> acc[C][B];
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+#pragma unroll
+                for (int a = 0; a < B; ++a) acc[i][a] = {0, 0};
+            const int u0 = cptr[cl], u1 = cptr[cl + 1];
+            for (int u = u0; u < u1; ++u) {
+                const int J = ccol[u];
+                cpx<T> x[B];
+#pragma unroll
+                for (int c = 0; c < B; ++c)
+                    x[c] = act ? d[static_cast<size_t>(J * B + c) * Rp + col] : cpx<T>{0, 0};
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    const int b = cblk[u * C + i];
+                    if (b < 0) continue;
+                    const T *sb = Sv + static_cast<size_t>(b) * B * B;
+#pragma unroll
+                    for (int a = 0; a < B; ++a) {
+#pragma unroll
+                        for (int c = 0; c < B; ++c) {
+                            const T sv = sb[a * B + c];
+                            acc[i][a].re = fma(sv, x[c].re, acc[i][a].re);
+                            acc[i][a].im = fma(sv, x[c].im, acc[i][a].im);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                const int I = cl * C + i;
+                if (I < nb && act) {
+#pragma unroll
+                    for (int a = 0; a < B; ++a) {
+                        const size_t e = static_cast<size_t>(I * B + a) * Rp + col;
+                        wout[e] = acc[i][a];
+                        const cpx<T> own = d[e];
+                        dot += static_cast<double>(own.re) * acc[i][a].re + static_cast<double>(own.im) * acc[i][a].im;
+                    }
+                }
+            }
+        }
+    }
+    __shared__ double red[kWavesPerBlock][64];
+    red[wv][lane] = dot;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double s = red[0][lane];
+#pragma unroll
+        for (int k = 1; k < kWavesPerBlock; ++k) s += red[k][lane];
+        partial[static_cast<size_t>(g) * Rp + col] = s;
+    }
+}
+
+// ------------------------------------------------------------------ Chebyshev step
+// One step of the Chebyshev iteration for S y = r on the interval
+// [theta - delta, theta + delta] fused with the product:
+//   res_k = r - S y_k,  d_k = c1 d_{k-1} + c2 res_k,  y_{k+1} = y_k + d_k.
+// FIRST: y_1 = r / theta and d_0 = r / theta are formed on the fly from r.
+// One gathered vector (y_k, or r when FIRST) and a partial ||res_k||^2.
+template <typename T, int B, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_cheb_step(
+    int nb, int Rp, int Lb, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    const T *__restrict__ Sv, const cpx<T> *__restrict__ y, const cpx<T> *__restrict__ r,
+    cpx<T> *__restrict__ dvec, cpx<T> *__restrict__ ynext, const int *__restrict__ skip, T inv_theta, T c1,
+    T c2, double *__restrict__ partial) {
+    int cx, g;
+    xcd_remap(cx, g);
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_id();
+    const int col = cx * 64 + lane;
+    const bool act = !skip[col];
+    double acc2 = 0.0;
+    const int I0 = g * Lb;
+    const int I1 = min(nb, I0 + Lb);
+    const cpx<T> *x = FIRST ? r : y;
+    if (__ballot(act) != 0) {
+        for (int I = I0 + wv; I < I1; I += kWavesPerBlock) {
+            cpx<T> aS[B], own[B];
+#pragma unroll
+            for (int a = 0; a < B; ++a) { aS[a] = {0, 0}; own[a] = {0, 0}; }
+            const int b0 = rowptr[I], b1 = rowptr[I + 1];
+#pragma unroll 2
+            for (int b = b0; b < b1; ++b) {
+                const int J = colidx[b];
+                const T *sb = Sv + static_cast<size_t>(b) * B * B;
+                cpx<T> xv[B];
+#pragma unroll
+                for (int c = 0; c < B; ++c)
+                    xv[c] = act ? x[static_cast<size_t>(J * B + c) * Rp + col] : cpx<T>{0, 0};
+                if (J == I) {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) own[c] = xv[c];
+                }
+#pragma unroll
+                for (int a = 0; a < B; ++a) {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) {
+                        const T sv = sb[a * B + c];
+                        aS[a].re = fma(sv, xv[c].re, aS[a].re);
+                        aS[a].im = fma(sv, xv[c].im, aS[a].im);
+                    }
+                }
+            }
+            if (!act) continue;
+#pragma unroll
+            for (int a = 0; a < B; ++a) {
+                const size_t e = static_cast<size_t>(I * B + a) * Rp + col;
+                cpx<T> yk, dprev;
+                const cpx<T> rv = FIRST ? own[a] : r[e];
+                cpx<T> Sy = aS[a];
+                if (FIRST) {
+                    yk = inv_theta * own[a];
+                    dprev = yk;
+                    Sy = inv_theta * Sy;
+                } else {
+                    yk = own[a];
+                    dprev = dvec[e];
+                }
+                const cpx<T> res = rv - Sy;
+                const cpx<T> dn = c1 * dprev + c2 * res;
+                dvec[e] = dn;
+                ynext[e] = yk + dn;
+                acc2 += static_cast<double>(res.re) * res.re + static_cast<double>(res.im) * res.im;
+            }
+        }
+    }
+    __shared__ double red[kWavesPerBlock][64];
+    red[wv][lane] = acc2;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double t = red[0][lane];
+#pragma unroll
+        for (int k = 1; k < kWavesPerBlock; ++k) t += red[k][lane];
+        partial[static_cast<size_t>(g) * Rp + col] = t;
+    }
+}
+
+template <typename T>
+void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, bool first, const T *Sv,
+                      const cpx<T> *y, const cpx<T> *r, cpx<T> *d, cpx<T> *ynext, const int *skip, double inv_theta,
+                      double c1, double c2, double *partial) {
+    // the fused step uses the one-block-row-per-wave layout (td.Lb rows per group)
+    dim3 grid(td.Rp / 64, td.Gs), block(kBlock);
+    const T it = static_cast<T>(inv_theta), a = static_cast<T>(c1), b = static_cast<T>(c2);
+#define GSC_CHEB(BB, F)                                                                                      \
+    k_cheb_step<T, BB, F><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(), Sv, \
+                                                  y, r, d, ynext, skip, it, a, b, partial)
+    if (pr.B == 4) { if (first) GSC_CHEB(4, true); else GSC_CHEB(4, false); }
+    else { if (first) GSC_CHEB(6, true); else GSC_CHEB(6, false); }
+#undef GSC_CHEB
+    GSC_HIP(hipGetLastError());
+}
+
+template void launch_cheb_step<double>(hipStream_t, const Pair &, const TileDims &, bool, const double *,
+                                       const c128 *, const c128 *, c128 *, c128 *, const int *, double, double,
+                                       double, double *);
+template void launch_cheb_step<float>(hipStream_t, const Pair &, const TileDims &, bool, const float *,
+                                      const c64 *, const c64 *, c64 *, c64 *, const int *, double, double,
+                                      double, double *);
+
 // ------------------------------------------------------------------ launchers
+// Row-group geometry of the product kernels.  Every reduction of their
+// partials uses td.Gs, so both variants launch exactly td.Gs row groups.
+void set_spmm_geometry(TileDims &td, const Pair &pr, int variant) {
+    td.variant = variant;
+    if (variant == 1) {
+        // one cluster per wave: 4 clusters per block of 4 waves
+        td.Gs = (div_up(pr.cl.nc, kWavesPerBlock) + 7) / 8 * 8;
+    } else {
+        int g = std::max(1, 2048 / std::max(1, td.Rp / 64));
+        g = static_cast<int>(std::min<int64_t>(g, (td.nb + 3) / 4));
+        td.Gs = (std::max(g, 1) + 7) / 8 * 8;
+    }
+    td.Lb = div_up(td.nb, td.Gs);
+}
+
+inline void cluster_geometry(const Pair &pr, const TileDims &td, int &gy, int &Lc) {
+    gy = td.Gs;
+    Lc = div_up(pr.cl.nc, td.Gs);
+}
 template <typename T>
 void launch_spmm_seed(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const T *Hv,
                       const cpx<T> *p, cpx<T> *q, const c128 *z, const int *seed, const int *skip,
-                      c128 *partial) {
+                      c128 *partial, unsigned long long *ctr) {
     dim3 grid(td.Rp / 64, td.Gs), block(kBlock);
+    if (td.variant == 1) {
+        int gy, Lc;
+        cluster_geometry(pr, td, gy, Lc);
+        if (pr.B == 4)
+            k_spmm_seed_cl<T, 4, 8><<<grid, block, 0, st>>>(td.nb, pr.cl.nc, td.Rp, Lc, pr.cl.ptr.get(),
+                                                            pr.cl.col.get(), pr.cl.blk.get(), Sv, Hv, p, q, z,
+                                                            seed, skip, partial);
+        else
+            k_spmm_seed_cl<T, 6, 4><<<grid, block, 0, st>>>(td.nb, pr.cl.nc, td.Rp, Lc, pr.cl.ptr.get(),
+                                                            pr.cl.col.get(), pr.cl.blk.get(), Sv, Hv, p, q, z,
+                                                            seed, skip, partial);
+        GSC_HIP(hipGetLastError());
+        return;
+    }
     if (pr.B == 4)
         k_spmm_seed<T, 4><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(),
-                                                  Sv, Hv, p, q, z, seed, skip, partial);
+                                                  Sv, Hv, p, q, z, seed, skip, partial, ctr);
     else
         k_spmm_seed<T, 6><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(),
-                                                  Sv, Hv, p, q, z, seed, skip, partial);
+                                                  Sv, Hv, p, q, z, seed, skip, partial, ctr);
     GSC_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_spmm_S(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const cpx<T> *d,
-                   cpx<T> *w, const int *skip, double *partial) {
+                   cpx<T> *w, const int *skip, double *partial, unsigned long long *ctr) {
     dim3 grid(td.Rp / 64, td.Gs), block(kBlock);
+    if (td.variant == 1) {
+        int gy, Lc;
+        cluster_geometry(pr, td, gy, Lc);
+        if (pr.B == 4)
+            k_spmm_S_cl<T, 4, 8><<<grid, block, 0, st>>>(td.nb, pr.cl.nc, td.Rp, Lc, pr.cl.ptr.get(),
+                                                         pr.cl.col.get(), pr.cl.blk.get(), Sv, d, w, skip, partial);
+        else
+            k_spmm_S_cl<T, 6, 4><<<grid, block, 0, st>>>(td.nb, pr.cl.nc, td.Rp, Lc, pr.cl.ptr.get(),
+                                                         pr.cl.col.get(), pr.cl.blk.get(), Sv, d, w, skip, partial);
+        GSC_HIP(hipGetLastError());
+        return;
+    }
     if (pr.B == 4)
         k_spmm_S<T, 4><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(), Sv,
-                                               d, w, skip, partial);
+                                               d, w, skip, partial, ctr);
     else
         k_spmm_S<T, 6><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(), Sv,
-                                               d, w, skip, partial);
+                                               d, w, skip, partial, ctr);
     GSC_HIP(hipGetLastError());
 }
 
 template void launch_spmm_seed<double>(hipStream_t, const Pair &, const TileDims &, const double *,
                                        const double *, const c128 *, c128 *, const c128 *, const int *,
-                                       const int *, c128 *);
+                                       const int *, c128 *, unsigned long long *);
 template void launch_spmm_seed<float>(hipStream_t, const Pair &, const TileDims &, const float *,
                                       const float *, const c64 *, c64 *, const c128 *, const int *,
-                                      const int *, c128 *);
+                                      const int *, c128 *, unsigned long long *);
 template void launch_spmm_S<double>(hipStream_t, const Pair &, const TileDims &, const double *,
-                                    const c128 *, c128 *, const int *, double *);
+                                    const c128 *, c128 *, const int *, double *, unsigned long long *);
 template void launch_spmm_S<float>(hipStream_t, const Pair &, const TileDims &, const float *, const c64 *,
-                                   c64 *, const int *, double *);
+                                   c64 *, const int *, double *, unsigned long long *);
 
 }  // namespace gsc

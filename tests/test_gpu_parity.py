@@ -266,3 +266,48 @@ def test_ased_vjp_matches_oracle(ctx, si216):
     F = api.ased_vjp(ctx, pair, s, scale, dH, dS)
     F0 = oased.forces(s, dH, dS, cc)
     assert rel(F, F0) < 1e-12
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_spmm_variants_in_solve(ctx, si216, kernel):
+    """Both product kernels (one block row per wave; register-blocked
+    clusters of block rows) give the LU solution."""
+    from paper_1002_1202_amd import api
+    c, S, H, _ = si216
+    print(f"case: spmm_kernel={kernel}", flush=True)
+    pair, _ = api.pair_from_system(ctx, c["system"])
+    rhs = c["rhs"][:12]
+    res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, spmm_kernel=kernel)
+    X = ogreen.solve_dense(H, S, c["z"], rhs)
+    assert rel(res.G_cols, X) < 1e-10
+
+
+@pytest.mark.parametrize("method", [1, 2])
+def test_inner_methods(ctx, si216, method):
+    """Inner S-solve by CG (1) or by the Chebyshev iteration on the Ritz
+    interval of the first CG solve (2): both reach the LU solution."""
+    from paper_1002_1202_amd import api
+    c, S, H, _ = si216
+    print(f"case: inner_method={method}", flush=True)
+    pair, _ = api.pair_from_system(ctx, c["system"])
+    rhs = c["rhs"][:24]
+    res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, inner_method=method, recheck=True)
+    X = ogreen.solve_dense(H, S, c["z"], rhs)
+    print(f"  iters={res.outer_iters} inner={res.inner_iters} err={rel(res.G_cols, X):.2e}", flush=True)
+    assert rel(res.G_cols, X) < 1e-10
+    assert res.res_true.max() < 1e-10
+
+
+def test_chebyshev_projected_water(ctx):
+    from paper_1002_1202_amd import api
+    c = configs.water_small(n_mol=40, n_rhs=16)
+    s = c["system"]
+    print("case: water40 projected + chebyshev", flush=True)
+    S, H, _ = oased.dense_pair(s)
+    pair, _ = api.pair_from_system(ctx, s)
+    rhs = c["rhs"]
+    proj = np.stack([rhs, (rhs + 5) % s.n], 1)
+    res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, carry="projected", proj=proj, inner_method=2)
+    X = ogreen.solve_dense(H, S, c["z"], rhs)
+    ref = np.take_along_axis(X, np.broadcast_to(proj[None], (X.shape[0],) + proj.shape), axis=2)
+    assert rel(res.G_proj, ref) < 1e-10
