@@ -314,3 +314,42 @@ def mulliken_band(ctx: Context, pair: Pair, z, w, orb, **opt):
                 inner_iters=st.inner_iters, switches=st.switches, restarts=st.restarts,
                 shift_rhs_iters=st.shift_rhs_iters, seconds=st.seconds)
     return q, e, eb.value, info
+
+
+def band_energy_vjp(ctx: Context, pair: Pair, z, w, grad_E: float = 1.0, dH=None, dS=None, **opt):
+    """Band energy over all orbitals and its gradients on the stored entries:
+    dH += grad_E dE/dH_bc, dS += grad_E dE/dS_bc (zeros when not given).
+    ``dH``/``dS`` may be numpy (host) or torch device tensors of shape
+    (nnzb, B, B).  Returns (dH, dS, E_band, info)."""
+    z = np.ascontiguousarray(z, dtype=np.complex128)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    K = z.shape[0]
+    opts = make_opts(**opt)
+    shape = (pair.nnzb, pair.block, pair.block)
+    if dH is None:
+        dH = np.zeros(shape)
+    if dS is None:
+        dS = np.zeros(shape)
+    mem = L.MEM_DEVICE if _is_device(dH) else L.MEM_HOST
+    if mem == L.MEM_HOST:
+        dH = np.ascontiguousarray(dH, dtype=np.float64)
+        dS = np.ascontiguousarray(dS, dtype=np.float64)
+    eb = C.c_double()
+    st, res, conv, _ = _stats(K, pair.n, False)
+    status = ctx.lib.gsc_band_energy_vjp(ctx.h, pair.h, K, _ptr(_complex_view(z)), _ptr(w), grad_E,
+                                         C.byref(opts), _vp(dH), _vp(dS), C.byref(eb), mem, C.byref(st))
+    L.check(status)
+    info = dict(status=status, res=res, converged=conv.astype(bool), outer_iters=st.outer_iters,
+                inner_iters=st.inner_iters, restarts=st.restarts, shift_rhs_iters=st.shift_rhs_iters,
+                seconds=st.seconds)
+    return dH, dS, eb.value, info
+
+
+def pair_values_device(pair: Pair):
+    """Copies of the pair's H, S values as torch device tensors."""
+    import torch
+    shape = (pair.nnzb, pair.block, pair.block)
+    H = torch.empty(shape, dtype=torch.float64, device=f"cuda:{pair.ctx.device}")
+    S = torch.empty_like(H)
+    L.check(pair.lib.gsc_pair_get_values(pair.h, _vp(H), _vp(S), L.MEM_DEVICE))
+    return H, S

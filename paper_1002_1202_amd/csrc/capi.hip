@@ -1,5 +1,6 @@
 // C ABI of the gsc library: argument validation, error mapping and the
 // reductions to Mulliken charges and band energy (Sec. 2.2).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -74,6 +75,28 @@ __global__ void k_sum(int n, const double *v, double *out) {
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = lds[0];
+}
+
+// Band-energy gradient on the stored entries from the weighted accumulators
+// of column c (projection m at pattern row b):
+//   dE/dH_bc = -(2/pi) sum_k w_k E_k Im (G S G)_bc = (2/pi) Im AD
+//   dE/dS_bc = -(2/pi) sum_k w_k E_k Im (G - z G S G)_bc = -(2/pi) Im (AG + AZ)
+// (G S G e_c = -dx/dz); e_c = -(2/pi) Im AG of the S e_c projection.
+__global__ void k_vjp_assemble(int R, int M, const c128 *acc, const int64_t *vidx, double grad_E, double *dH,
+                               double *dS, double *e_col) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<int64_t>(R) * M) return;
+    const int c = static_cast<int>(t / M), m = static_cast<int>(t % M);
+    const c128 *A = acc + static_cast<size_t>(t) * 3;
+    const double f = 2.0 / M_PI;
+    if (m == M - 1) {
+        e_col[c] = -f * A[0].im;
+        return;
+    }
+    const int64_t v = vidx[t];
+    if (v < 0) return;
+    dH[v] += grad_E * f * A[1].im;
+    dS[v] += grad_E * (-f) * (A[0].im + A[2].im);
 }
 
 __global__ void k_pad_cols(int N, int R, int Rp, const c128 *in, c128 *out, int to_padded) {
@@ -407,10 +430,102 @@ gsc_status gsc_mulliken_band(gsc_ctx *ctx, const gsc_pair *pair, int nshift, con
 gsc_status gsc_band_energy_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const double *z, const double *w,
                                double grad_E, const gsc_opts *opts, double *dHval, double *dSval, double *e_band,
                                int mem, gsc_stats *stats) {
-    (void)ctx; (void)pair; (void)nshift; (void)z; (void)w; (void)grad_E; (void)opts;
-    (void)dHval; (void)dSval; (void)e_band; (void)mem; (void)stats;
-    set_last_error("gsc_band_energy_vjp: not built yet");
-    return GSC_E_UNSUPPORTED;
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr && pair != nullptr, "ctx/pair must not be NULL");
+        gsc_opts o;
+        gsc_opts_default(&o);
+        if (opts) o = *opts;
+        validate_opts(o);
+        validate_shifts(nshift, z, o.seed_index);
+        GSC_REQUIRE(w != nullptr, "weights must not be NULL");
+        GSC_REQUIRE(dHval != nullptr && dSval != nullptr, "dHval/dSval must not be NULL");
+        GSC_REQUIRE(std::isfinite(grad_E), "grad_E must be finite");
+        const Pair &p = pair->p;
+        DeviceGuard g(ctx->c.device);
+        hipStream_t st = ctx->c.stream;
+        const int64_t N = p.n;
+        const int B = p.B;
+        o.carry = GSC_CARRY_PROJECTED;
+        // projections of column c: every row b with a stored (b, c) entry,
+        // i.e. the orbitals of the column blocks of c's block row (symmetric
+        // pattern); the stored entry (b, c) sits in the mirror block
+        int max_len = 0;
+        for (int64_t I = 0; I < p.nb; ++I)
+            max_len = std::max<int>(max_len, static_cast<int>(p.h_rowptr[I + 1] - p.h_rowptr[I]));
+        const int Mu = max_len * B;
+        GSC_REQUIRE(Mu + 1 <= 1024, "too many stored entries per column for the projected backward");
+        std::vector<int32_t> mirror(p.nnzb);
+        GSC_HIP(hipMemcpy(mirror.data(), p.mirror.get(), p.nnzb * 4, hipMemcpyDeviceToHost));
+        ProjSpec ps;
+        ps.M = Mu;
+        ps.srow = true;
+        ps.idx.assign(static_cast<size_t>(N) * Mu, 0);
+        const int M = Mu + 1;
+        std::vector<int64_t> vidx(static_cast<size_t>(N) * M, -1);
+        for (int64_t c = 0; c < N; ++c) {
+            const int64_t I = c / B, a = c % B;
+            int m = 0;
+            for (int64_t blk = p.h_rowptr[I]; blk < p.h_rowptr[I + 1]; ++blk) {
+                const int64_t J = p.h_colidx[blk], mb = mirror[blk];
+                for (int be = 0; be < B; ++be, ++m) {
+                    ps.idx[static_cast<size_t>(c) * Mu + m] = static_cast<int32_t>(J * B + be);
+                    vidx[static_cast<size_t>(c) * M + m] = (mb * B + be) * B + a;
+                }
+            }
+            for (; m < Mu; ++m) ps.idx[static_cast<size_t>(c) * Mu + m] = static_cast<int32_t>(c);
+        }
+        std::vector<int64_t> rhs(N);
+        for (int64_t c = 0; c < N; ++c) rhs[c] = c;
+        std::vector<double> wE(nshift);
+        for (int k = 0; k < nshift; ++k) wE[k] = w[k] * z[2 * k];
+        DevBuf<double> dwE(nshift);
+        GSC_HIP(hipMemcpyAsync(dwE.get(), wE.data(), nshift * 8, hipMemcpyHostToDevice, st));
+        DevBuf<c128> acc(static_cast<size_t>(N) * M * 3);
+        GSC_HIP(hipMemsetAsync(acc.get(), 0, acc.n * sizeof(c128), st));
+        SolveRequest req;
+        req.pair = &p;
+        req.K = nshift;
+        req.z = z;
+        req.R = static_cast<int>(N);
+        req.rhs_idx = rhs.data();
+        req.opts = o;
+        req.out_mem = GSC_MEM_DEVICE;
+        req.stats = stats;
+        req.proj = &ps;
+        req.vjp = true;
+        req.wE = dwE.get();
+        req.vjp_acc = acc.get();
+        const gsc_status s = run_solve(ctx->c, req);
+        // assemble into device buffers, then copy per mem
+        const size_t nv = static_cast<size_t>(p.nnzb) * B * B;
+        DevBuf<double> tH, tS;
+        double *pH = dHval, *pS = dSval;
+        if (mem != GSC_MEM_DEVICE) {
+            tH.alloc(nv);
+            tS.alloc(nv);
+            GSC_HIP(hipMemcpyAsync(tH.get(), dHval, nv * 8, hipMemcpyHostToDevice, st));
+            GSC_HIP(hipMemcpyAsync(tS.get(), dSval, nv * 8, hipMemcpyHostToDevice, st));
+            pH = tH.get();
+            pS = tS.get();
+        }
+        DevBuf<int64_t> dv(vidx.size());
+        DevBuf<double> ecol(N), eb(1);
+        GSC_HIP(hipMemcpyAsync(dv.get(), vidx.data(), vidx.size() * 8, hipMemcpyHostToDevice, st));
+        const int64_t tot = N * M;
+        k_vjp_assemble<<<div_up(tot, 256), 256, 0, st>>>(static_cast<int>(N), M, acc.get(), dv.get(), grad_E, pH, pS,
+                                                         ecol.get());
+        k_sum<<<1, 256, 0, st>>>(static_cast<int>(N), ecol.get(), eb.get());
+        GSC_HIP(hipGetLastError());
+        if (mem != GSC_MEM_DEVICE) {
+            GSC_HIP(hipMemcpyAsync(dHval, tH.get(), nv * 8, hipMemcpyDeviceToHost, st));
+            GSC_HIP(hipMemcpyAsync(dSval, tS.get(), nv * 8, hipMemcpyDeviceToHost, st));
+        }
+        double ebh = 0.0;
+        GSC_HIP(hipMemcpyAsync(&ebh, eb.get(), 8, hipMemcpyDeviceToHost, st));
+        GSC_HIP(hipStreamSynchronize(st));
+        if (e_band) *e_band = ebh;
+        return s;
+    });
 }
 
 gsc_status gsc_profile_enable(gsc_ctx *ctx, int on) {

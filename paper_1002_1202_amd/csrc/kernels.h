@@ -43,6 +43,10 @@ struct ShiftState {
     double *res;              // recursive residual estimate at freeze / exit
     int *last;                // last active step (kFrozenNever while active)
     c128 *ra, *rb, *rc;       // [m][K][Rp] shift-update coefficients
+    // z-derivative carry (null unless requested): d/dz_k of pi, of the
+    // restart weight and of the three update coefficients
+    c128 *dpi, *dpi_prev, *dpi_next, *domega;
+    c128 *rda, *rdb, *rdc;
 };
 
 struct TileDims {

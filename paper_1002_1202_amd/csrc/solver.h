@@ -38,6 +38,11 @@ struct SolveRequest {
     c128 *proj_out = nullptr;           // device [K][R][M]
     // (S G)_aa for unit rhs: device [K][R] complex (full carry Mulliken path)
     c128 *sg_diag = nullptr;
+    // backward: z-derivative carry with quadrature-weighted accumulation,
+    // wE = w_k Re z_k (device [K]); acc device [R][M][3] (M = proj M + srow)
+    bool vjp = false;
+    const double *wE = nullptr;
+    c128 *vjp_acc = nullptr;
     gsc_stats *stats = nullptr;
 };
 

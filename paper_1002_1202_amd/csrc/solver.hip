@@ -95,6 +95,12 @@ __global__ void k_init_shifts(int K, int R, int Rp, ShiftState ss) {
     ss.omega[t] = {1.0, 0.0};
     ss.res[t] = 0.0;
     ss.last[t] = c < R ? kFrozenNever : -1;
+    if (ss.dpi != nullptr) {
+        ss.dpi[t] = {0.0, 0.0};
+        ss.dpi_prev[t] = {0.0, 0.0};
+        ss.dpi_next[t] = {0.0, 0.0};
+        ss.domega[t] = {0.0, 0.0};
+    }
 }
 
 // r = b; res = d = r; partial ||r||^2.  Unit rhs (rhs != null) or dense B[c][i].
@@ -249,9 +255,21 @@ __global__ __launch_bounds__(kBlock) void k_ctrl(int K, int Rp, int G, int n, in
         const c128 pin = lead * pi + tail * (pi - pim);
         ss.pi_next[idx] = pin;
         const c128 q = cdiv(pim, pi);
+        const c128 ak = cdiv(alpha * pi, pin);      // alpha^k_n
         ss.ra[slot * KR + idx] = cdiv(c128{1.0, 0.0}, pi);
         ss.rb[slot * KR + idx] = (q * q) * cs.beta_prev[c];
-        ss.rc[slot * KR + idx] = ss.omega[idx] * cdiv(alpha * pi, pin);
+        ss.rc[slot * KR + idx] = ss.omega[idx] * ak;
+        if (ss.dpi != nullptr) {
+            // d/dz_k of the recurrence at a fixed seed process (delta' = 1)
+            const c128 dpi = ss.dpi[idx], dpim = ss.dpi_prev[idx];
+            const c128 dpin = alpha * pi + lead * dpi + tail * (dpi - dpim);
+            ss.dpi_next[idx] = dpin;
+            const c128 dak = cdiv(alpha * (dpi * pin - pi * dpin), pin * pin);
+            const c128 dbk = cdiv(2.0 * cs.beta_prev[c] * q * (dpim * pi - pim * dpi), pi * pi);
+            ss.rda[slot * KR + idx] = cdiv(c128{-dpi.re, -dpi.im}, pi * pi);
+            ss.rdb[slot * KR + idx] = dbk;
+            ss.rdc[slot * KR + idx] = ss.domega[idx] * ak + ss.omega[idx] * dak;
+        }
     }
     s_cnt[threadIdx.x] = cnt;
     __syncthreads();
@@ -273,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_ctrl(int K, int Rp, int G, int n, in
 // rho' = r'^T r; beta; pi shift; freeze; seed switch / collinear restart.
 __global__ __launch_bounds__(kBlock) void k_post(int K, int Rp, int G, int n, int full_carry,
                                                  const c128 *partial, double tol, ColState cs,
-                                                 ShiftState ss, c128 *proj_h, int M) {
+                                                 ShiftState ss, c128 *proj_h, c128 *proj_dh, int M) {
     __shared__ c128 lds[kBlock];
     __shared__ double s_res[kBlock];
     __shared__ int s_k[kBlock];
@@ -295,6 +313,10 @@ __global__ __launch_bounds__(kBlock) void k_post(int K, int Rp, int G, int n, in
         const c128 pin = ss.pi_next[idx];
         ss.pi_prev[idx] = ss.pi[idx];
         ss.pi[idx] = pin;
+        if (ss.dpi != nullptr) {
+            ss.dpi_prev[idx] = ss.dpi[idx];
+            ss.dpi[idx] = ss.dpi_next[idx];
+        }
         const double res = cabs(ss.omega[idx]) * rn / (cabs(pin) * bn);
         ss.res[idx] = res;
         if (!(res > tol)) {
@@ -373,15 +395,32 @@ __global__ __launch_bounds__(kBlock) void k_post(int K, int Rp, int G, int n, in
             const size_t idx = static_cast<size_t>(k) * Rp + c;
             ss.pi[idx] = cdiv(ss.pi[idx], cc);
             ss.pi_prev[idx] = cdiv(ss.pi_prev[idx], ccm);
+            if (ss.dpi != nullptr) {
+                ss.dpi[idx] = cdiv(ss.dpi[idx], cc);
+                ss.dpi_prev[idx] = cdiv(ss.dpi_prev[idx], ccm);
+            }
         }
     } else if (sw == 2) {
         for (int k = threadIdx.x; k < K; k += kBlock) {
             const size_t idx = static_cast<size_t>(k) * Rp + c;
-            if (ss.last[idx] == kFrozenNever) ss.omega[idx] = cdiv(ss.omega[idx], ss.pi[idx]);
+            if (ss.last[idx] == kFrozenNever) {
+                const c128 pik = ss.pi[idx];
+                if (ss.dpi != nullptr)
+                    // omega_k / pi_k(z): d/dz = domega/pi - omega dpi / pi^2
+                    ss.domega[idx] = cdiv(ss.domega[idx], pik) - cdiv(ss.omega[idx] * ss.dpi[idx], pik * pik);
+                ss.omega[idx] = cdiv(ss.omega[idx], pik);
+            }
             ss.pi[idx] = {1.0, 0.0};
             ss.pi_prev[idx] = {1.0, 0.0};
+            if (ss.dpi != nullptr) {
+                ss.dpi[idx] = {0.0, 0.0};
+                ss.dpi_prev[idx] = {0.0, 0.0};
+            }
             if (proj_h != nullptr)
-                for (int m = 0; m < M; ++m) proj_h[(static_cast<size_t>(k) * Rp + c) * M + m] = {0, 0};
+                for (int m = 0; m < M; ++m) {
+                    proj_h[(static_cast<size_t>(k) * Rp + c) * M + m] = {0, 0};
+                    if (proj_dh != nullptr) proj_dh[(static_cast<size_t>(k) * Rp + c) * M + m] = {0, 0};
+                }
         }
     }
 }
@@ -757,6 +796,66 @@ __global__ __launch_bounds__(kBlock) void k_proj_update(int K, int Rp, int Mu, i
     }
 }
 
+// Projected carry with the z-derivative, accumulating the quadrature-weighted
+// sums the band-energy gradient needs (wE_k = w_k Re z_k):
+//   AG_m += wE_k  dG_{k,m},   AD_m += wE_k  d(dG)_{k,m},   AZ_m += wE_k z_k d(dG)_{k,m}
+// where dG_{k,m} is this step's increment of c_m^T x^k and d(dG) that of its
+// z-derivative.  One thread per projection m loops over the shifts, so each
+// accumulator has a single owner (no reduction, deterministic).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_proj_update_vjp(
+    int K, int Rp, int Mu, int srow, int slot, int B, const int32_t *rowptr, const int32_t *colidx,
+    const double *Sval, const int64_t *rhs, const int32_t *pidx, ColState cs, ShiftState ss, const cpx<T> *rp,
+    c128 *h, c128 *dh, const double *wE, c128 *acc) {
+    extern __shared__ c128 cr[];
+    const int c = blockIdx.x;
+    if (cs.done[c]) return;
+    const int M = Mu + srow;
+    for (int m = threadIdx.x; m < Mu; m += kBlock)
+        cr[m] = ccast<double>(rp[static_cast<size_t>(pidx[static_cast<size_t>(c) * Mu + m]) * Rp + c]);
+    if (srow) {
+        __shared__ c128 lds[kBlock];
+        const int64_t a = rhs[c];
+        const int I = static_cast<int>(a / B), ar = static_cast<int>(a % B);
+        const int b0 = rowptr[I], b1 = rowptr[I + 1];
+        c128 sacc{0, 0};
+        for (int t = threadIdx.x; t < (b1 - b0) * B; t += kBlock) {
+            const int b = b0 + t / B, cc = t % B;
+            sacc = sacc + Sval[(static_cast<size_t>(b) * B + ar) * B + cc] *
+                              ccast<double>(rp[static_cast<size_t>(colidx[b] * B + cc) * Rp + c]);
+        }
+        const c128 tot = block_sum(sacc, lds);
+        if (threadIdx.x == 0) cr[Mu] = tot;
+    }
+    __syncthreads();
+    const size_t KR = static_cast<size_t>(K) * Rp;
+    for (int m = threadIdx.x; m < M; m += kBlock) {
+        const c128 crm = cr[m];
+        c128 ag{0, 0}, ad{0, 0}, az{0, 0};
+        for (int k = 0; k < K; ++k) {
+            const size_t idx = static_cast<size_t>(k) * Rp + c;
+            if (ss.last[idx] != kFrozenNever) continue;
+            const size_t sidx = static_cast<size_t>(slot) * KR + idx;
+            const size_t o = idx * M + m;
+            const c128 hold = h[o], dhold = dh[o];
+            const c128 hv = ss.ra[sidx] * crm + ss.rb[sidx] * hold;
+            const c128 dhv = ss.rda[sidx] * crm + ss.rdb[sidx] * hold + ss.rb[sidx] * dhold;
+            h[o] = hv;
+            dh[o] = dhv;
+            const c128 dg = ss.rc[sidx] * hv;
+            const c128 ddg = ss.rdc[sidx] * hv + ss.rc[sidx] * dhv;
+            const double we = wE[k];
+            ag = ag + we * dg;
+            ad = ad + we * ddg;
+            az = az + we * (ss.z[k] * ddg);
+        }
+        c128 *A = acc + (static_cast<size_t>(c) * M + m) * 3;
+        A[0] = A[0] + ag;
+        A[1] = A[1] + ad;
+        A[2] = A[2] + az;
+    }
+}
+
 // ------------------------------------------------------------------ outputs
 // (S x^k)_a for unit rhs a = rhs[c] from the full-carry iterates.
 template <typename T>
@@ -867,6 +966,7 @@ template <typename T> struct Tile {
     DevBuf<double> cg_ha, cg_hb;
     // shift state
     DevBuf<c128> s_pi, s_pi_prev, s_pi_next, s_omega, s_ra, s_rb, s_rc;
+    DevBuf<c128> s_dpi, s_dpi_prev, s_dpi_next, s_domega, s_rda, s_rdb, s_rdc, dh;
     DevBuf<double> s_res;
     DevBuf<int> s_last;
     // partials
@@ -895,6 +995,8 @@ template <typename T> struct Tile {
         s.z = z; s.pi = s_pi.get(); s.pi_prev = s_pi_prev.get(); s.pi_next = s_pi_next.get();
         s.omega = s_omega.get(); s.res = s_res.get(); s.last = s_last.get();
         s.ra = s_ra.get(); s.rb = s_rb.get(); s.rc = s_rc.get();
+        s.dpi = s_dpi.get(); s.dpi_prev = s_dpi_prev.get(); s.dpi_next = s_dpi_next.get();
+        s.domega = s_domega.get(); s.rda = s_rda.get(); s.rdb = s_rdb.get(); s.rdc = s_rdc.get();
         return s;
     }
 };
@@ -980,7 +1082,13 @@ template <typename T> class TileSolver {
             t_.srow = (ps.srow && drhs_ != nullptr) ? 1 : 0;
             const int M = t_.Mu + t_.srow;
             t_.h.alloc(KR * M);
-            t_.gacc.alloc(KR * M);
+            if (req_.vjp) {
+                t_.dh.alloc(KR * M);
+                t_.s_dpi.alloc(KR); t_.s_dpi_prev.alloc(KR); t_.s_dpi_next.alloc(KR); t_.s_domega.alloc(KR);
+                t_.s_rda.alloc(KR * td.m); t_.s_rdb.alloc(KR * td.m); t_.s_rdc.alloc(KR * td.m);
+            } else {
+                t_.gacc.alloc(KR * M);
+            }
             if (t_.Mu > 0) {
                 std::vector<int32_t> idx(static_cast<size_t>(td.Rp) * t_.Mu, 0);
                 for (int c = 0; c < td.R; ++c)
@@ -1009,10 +1117,9 @@ template <typename T> class TileSolver {
             k_zero_shifted<T><<<div_up(tot, 256), 256, 0, st_>>>(td.K, td.R, td.N, t_.ldk, t_.P.get());
             k_zero_shifted<T><<<div_up(tot, 256), 256, 0, st_>>>(td.K, td.R, td.N, ldk_x_, t_.X);
         }
-        if (t_.h.get()) {
-            GSC_HIP(hipMemsetAsync(t_.h.get(), 0, t_.h.n * sizeof(c128), st_));
-            GSC_HIP(hipMemsetAsync(t_.gacc.get(), 0, t_.gacc.n * sizeof(c128), st_));
-        }
+        if (t_.h.get()) GSC_HIP(hipMemsetAsync(t_.h.get(), 0, t_.h.n * sizeof(c128), st_));
+        if (t_.gacc.get()) GSC_HIP(hipMemsetAsync(t_.gacc.get(), 0, t_.gacc.n * sizeof(c128), st_));
+        if (t_.dh.get()) GSC_HIP(hipMemsetAsync(t_.dh.get(), 0, t_.dh.n * sizeof(c128), st_));
         GSC_HIP(hipGetLastError());
         // r = b, r'_0 = S^{-1} b, p = r'_0, rho = r'^T r
         k_init_rhs<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, td.R, drhs_, dB_, t_.r.get(), t_.res.get(),
@@ -1064,7 +1171,7 @@ template <typename T> class TileSolver {
             prof_.end(st_);
             prof_.begin(st_, KP_POST, 0.0);
             k_post<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.G, n, full_ ? 1 : 0, t_.part_c.get(), o.tol, cs,
-                                              ss, t_.h.get(), t_.Mu + t_.srow);
+                                              ss, t_.h.get(), t_.dh.get(), t_.Mu + t_.srow);
             prof_.end(st_);
             GSC_HIP(hipGetLastError());
             const Status s = check_status(true);
@@ -1147,7 +1254,7 @@ template <typename T> class TileSolver {
                                                                req_.sg_diag, nrhs_total, r0_);
                 GSC_HIP(hipGetLastError());
             }
-        } else if (req_.proj_out != nullptr) {
+        } else if (req_.proj_out != nullptr && t_.gacc.get() != nullptr) {
             const int M = t_.Mu + t_.srow;
             const int64_t tot = static_cast<int64_t>(td.K) * td.R * M;
             k_store_proj<<<div_up(tot, 256), 256, 0, st_>>>(td.K, td.R, td.Rp, M, t_.gacc.get(), req_.proj_out,
@@ -1397,9 +1504,17 @@ template <typename T> class TileSolver {
         const int M = t_.Mu + t_.srow;
         const size_t shm = static_cast<size_t>(M) * sizeof(c128);
         prof_.begin(st_, KP_PROJ_UPDATE, 0.0);
-        k_proj_update<T><<<td.Rp, kBlock, shm, st_>>>(td.K, td.Rp, t_.Mu, t_.srow, slot, td.B, pr_.rowptr.get(),
-                                                     pr_.colidx.get(), pr_.S.get(), drhs_, t_.pidx.get(), cs, ss,
-                                                     rp, t_.h.get(), t_.gacc.get());
+        if (req_.vjp) {
+            const int M = t_.Mu + t_.srow;
+            k_proj_update_vjp<T><<<td.Rp, kBlock, shm, st_>>>(
+                td.K, td.Rp, t_.Mu, t_.srow, slot, td.B, pr_.rowptr.get(), pr_.colidx.get(), pr_.S.get(), drhs_,
+                t_.pidx.get(), cs, ss, rp, t_.h.get(), t_.dh.get(), req_.wE,
+                req_.vjp_acc + static_cast<size_t>(r0_) * M * 3);
+        } else {
+            k_proj_update<T><<<td.Rp, kBlock, shm, st_>>>(td.K, td.Rp, t_.Mu, t_.srow, slot, td.B, pr_.rowptr.get(),
+                                                         pr_.colidx.get(), pr_.S.get(), drhs_, t_.pidx.get(), cs, ss,
+                                                         rp, t_.h.get(), t_.gacc.get());
+        }
         prof_.end(st_);
         GSC_HIP(hipGetLastError());
     }
@@ -1468,6 +1583,14 @@ gsc_status solve_typed(Ctx &ctx, SolveRequest &req) {
         const double per_col = 2.0 * req.K * N * sizeof(cpx<T>) + 16.0 * N * sizeof(cpx<T>);
         const int fit = static_cast<int>(0.8 * static_cast<double>(freeb) / per_col);
         Rt = std::max(1, std::min(Rt, fit));
+    }
+    if (!full && o.rhs_tile <= 0) {
+        size_t freeb = 0, totalb = 0;
+        GSC_HIP(hipMemGetInfo(&freeb, &totalb));
+        const int M = (req.proj ? req.proj->M : 0) + 1;
+        const double per_col = 10.0 * N * sizeof(cpx<T>) + static_cast<double>(req.K) * (M * 2.0 * 16 + 256.0);
+        const int fit = static_cast<int>(0.6 * static_cast<double>(freeb) / per_col);
+        Rt = std::max(64, std::min(Rt, fit));
     }
     Rt = std::max(1, std::min(Rt, req.R));
     int m = o.fuse_steps > 0 ? std::min(o.fuse_steps, kMaxFuse) : (full ? 8 : 1);
