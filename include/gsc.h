@@ -92,7 +92,9 @@ typedef struct {
                               widened by 10 %, with a residual check and extra
                               steps if the check fails; auto = 2 when the
                               interval is positive, else 1                     */
-    int reserved[6];
+    int graph_iters;       /* [0 = 4] gsc_solve_batched: outer iterations per
+                              captured hipGraph launch (between status polls)  */
+    int reserved[5];
 } gsc_opts;
 
 /* Statistics.  The three arrays are caller-owned HOST arrays of
@@ -246,8 +248,14 @@ gsc_status gsc_profile_select(gsc_ctx *ctx, const char *kernel);
 gsc_status gsc_profile_read(gsc_ctx *ctx, const char *kernel, double *total_ms, long long *launches,
                             double *bytes);
 
-/* Many independent systems in one launch sequence (each system's shifts,
- * rhs and outputs as in gsc_problem; projected carry, G_jj and charges). */
+/* Many independent systems solved together (each system's shifts, rhs and
+ * outputs as in gsc_problem).  Projected carry: G_jj for every unit rhs e_j
+ * and, when w is given, the Mulliken charge and band-energy contribution of
+ * orbital j.  Every (system, rhs tile) is one job; after its set-up each job
+ * iterates as a captured hipGraph of opts->graph_iters outer iterations,
+ * jobs run concurrently on several streams and a host scheduler polls their
+ * completion events (longest jobs first).  Returns GSC_NOT_CONVERGED if any
+ * system did not converge (outputs written), a negative status on error. */
 gsc_status gsc_solve_batched(gsc_ctx *ctx, int nsys, const gsc_problem *problems,
                              const gsc_opts *opts);
 

@@ -192,7 +192,7 @@ def spmm(ctx: Context, pair: Pair, X, alpha_S):
 
 def make_opts(tol=1e-10, max_iter=5000, inner_tol=0.0, inner_max_iter=200, precision="fp64",
               carry="full", seed_index=-1, fuse_steps=0, rhs_tile=0, recheck=False,
-              spmm_kernel=0, inner_method=0) -> L.Opts:
+              spmm_kernel=0, inner_method=0, graph_iters=0) -> L.Opts:
     o = L.Opts()
     L.load().gsc_opts_default(C.byref(o))
     o.tol, o.max_iter, o.inner_tol, o.inner_max_iter = tol, max_iter, inner_tol, inner_max_iter
@@ -201,6 +201,7 @@ def make_opts(tol=1e-10, max_iter=5000, inner_tol=0.0, inner_max_iter=200, preci
     o.seed_index, o.fuse_steps, o.rhs_tile, o.recheck = seed_index, fuse_steps, rhs_tile, int(recheck)
     o.spmm_kernel = spmm_kernel
     o.inner_method = inner_method
+    o.graph_iters = graph_iters
     return o
 
 
@@ -353,3 +354,48 @@ def pair_values_device(pair: Pair):
     S = torch.empty_like(H)
     L.check(pair.lib.gsc_pair_get_values(pair.h, _vp(H), _vp(S), L.MEM_DEVICE))
     return H, S
+
+
+def solve_batched(ctx: Context, problems, **opt):
+    """Solve many systems together (projected carry).  ``problems``: list of
+    dicts with keys pair, z, rhs and optionally w.  Returns a list of dicts
+    with G_jj (K, R) complex, q and e (R,) when w was given, and stats."""
+    import torch
+    opts = make_opts(**opt)
+    n = len(problems)
+    arr = (L.Problem * n)()
+    keep = []
+    outs = []
+    dev = f"cuda:{ctx.device}"
+    for i, pb in enumerate(problems):
+        z = np.ascontiguousarray(pb["z"], dtype=np.complex128)
+        rhs = np.ascontiguousarray(pb["rhs"], dtype=np.int64)
+        K, R = z.shape[0], rhs.shape[0]
+        zv = _complex_view(z)
+        g = torch.empty((K, R), dtype=torch.complex128, device=dev)
+        w = pb.get("w")
+        wv = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        q = torch.empty(R, dtype=torch.float64, device=dev) if w is not None else None
+        e = torch.empty(R, dtype=torch.float64, device=dev) if w is not None else None
+        st, res, conv, _ = _stats(K, R, False)
+        arr[i].pair = pb["pair"].h
+        arr[i].nshift = K
+        arr[i].z = _ptr(zv)
+        arr[i].nrhs = R
+        arr[i].rhs_idx = _ptr(rhs, C.c_int64)
+        arr[i].w = _ptr(wv) if wv is not None else None
+        arr[i].g_diag = _vp(g)
+        arr[i].q_orb = _vp(q) if q is not None else None
+        arr[i].e_orb = _vp(e) if e is not None else None
+        arr[i].stats = C.pointer(st)
+        keep.append((zv, rhs, wv, st))
+        outs.append(dict(G_jj=g, q=q, e=e, res=res, converged=conv, stats=st))
+    status = ctx.lib.gsc_solve_batched(ctx.h, n, arr, C.byref(opts))
+    L.check(status)
+    for o in outs:
+        st = o.pop("stats")
+        o.update(status=status, outer_iters=st.outer_iters, inner_iters=st.inner_iters,
+                 shift_rhs_iters=st.shift_rhs_iters, seconds=st.seconds,
+                 converged=o["converged"].astype(bool))
+    del keep
+    return outs

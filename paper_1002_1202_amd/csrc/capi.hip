@@ -572,10 +572,93 @@ gsc_status gsc_profile_read(gsc_ctx *ctx, const char *kernel, double *total_ms, 
     });
 }
 
+__global__ void k_extract_slot(int64_t n, int M, int slot, const c128 *in, c128 *out) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = in[t * M + slot];
+}
+
 gsc_status gsc_solve_batched(gsc_ctx *ctx, int nsys, const gsc_problem *problems, const gsc_opts *opts) {
-    (void)ctx; (void)nsys; (void)problems; (void)opts;
-    set_last_error("gsc_solve_batched: not built yet");
-    return GSC_E_UNSUPPORTED;
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr && problems != nullptr && nsys >= 1, "bad batched arguments");
+        gsc_opts o;
+        gsc_opts_default(&o);
+        if (opts) o = *opts;
+        validate_opts(o);
+        GSC_REQUIRE(o.graph_iters >= 0, "graph_iters must be >= 0");
+        o.carry = GSC_CARRY_PROJECTED;
+        const int graph_iters = o.graph_iters > 0 ? o.graph_iters : 4;
+        DeviceGuard g(ctx->c.device);
+        hipStream_t st = ctx->c.stream;
+        std::vector<ProjSpec> specs(nsys);
+        std::vector<SolveRequest> reqs(nsys);
+        std::vector<DevBuf<c128>> outs(nsys);
+        for (int i = 0; i < nsys; ++i) {
+            const gsc_problem &pb = problems[i];
+            GSC_REQUIRE(pb.pair != nullptr, "problem pair must not be NULL");
+            validate_shifts(pb.nshift, pb.z, o.seed_index);
+            GSC_REQUIRE(pb.nrhs >= 1 && pb.rhs_idx != nullptr, "each problem needs unit right-hand sides");
+            const Pair &p = pb.pair->p;
+            for (int r = 0; r < pb.nrhs; ++r)
+                GSC_REQUIRE(pb.rhs_idx[r] >= 0 && pb.rhs_idx[r] < p.n, "rhs index out of range");
+            specs[i].M = 1;
+            specs[i].srow = true;
+            specs[i].idx.resize(pb.nrhs);
+            for (int r = 0; r < pb.nrhs; ++r) specs[i].idx[r] = static_cast<int32_t>(pb.rhs_idx[r]);
+            outs[i].alloc(static_cast<size_t>(pb.nshift) * pb.nrhs * 2);
+            SolveRequest &rq = reqs[i];
+            rq.pair = &p;
+            rq.K = pb.nshift;
+            rq.z = pb.z;
+            rq.R = pb.nrhs;
+            rq.rhs_idx = pb.rhs_idx;
+            rq.opts = o;
+            rq.out_mem = GSC_MEM_DEVICE;
+            rq.proj = &specs[i];
+            rq.proj_out = outs[i].get();
+            rq.stats = pb.stats;
+            if (pb.stats) {
+                pb.stats->inner_iters = 0;
+                pb.stats->shift_rhs_iters = 0;
+                pb.stats->switches = 0;
+                pb.stats->restarts = 0;
+            }
+        }
+        hipEvent_t e0, e1;
+        GSC_HIP(hipEventCreate(&e0));
+        GSC_HIP(hipEventCreate(&e1));
+        GSC_HIP(hipDeviceSynchronize());
+        GSC_HIP(hipEventRecord(e0, st));
+        std::vector<int> iters;
+        const gsc_status s = run_batched(ctx->c, reqs, graph_iters, 8, iters);
+        GSC_HIP(hipDeviceSynchronize());
+        GSC_HIP(hipEventRecord(e1, st));
+        GSC_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        GSC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        for (int i = 0; i < nsys; ++i) {
+            const gsc_problem &pb = problems[i];
+            const int64_t n = static_cast<int64_t>(pb.nshift) * pb.nrhs;
+            if (pb.g_diag)
+                k_extract_slot<<<div_up(n, 256), 256, 0, st>>>(n, 2, 0, outs[i].get(), reinterpret_cast<c128 *>(pb.g_diag));
+            if (pb.w && (pb.q_orb || pb.e_orb)) {
+                DevBuf<c128> dz(pb.nshift);
+                DevBuf<double> dw(pb.nshift), dq(pb.nrhs), de(pb.nrhs);
+                GSC_HIP(hipMemcpyAsync(dz.get(), pb.z, pb.nshift * sizeof(c128), hipMemcpyHostToDevice, st));
+                GSC_HIP(hipMemcpyAsync(dw.get(), pb.w, pb.nshift * sizeof(double), hipMemcpyHostToDevice, st));
+                k_mulliken<<<div_up(pb.nrhs, 256), 256, 0, st>>>(pb.nshift, pb.nrhs, outs[i].get() + 1,
+                                                                 static_cast<size_t>(pb.nrhs) * 2, 2, dz.get(),
+                                                                 dw.get(), pb.q_orb ? pb.q_orb : dq.get(),
+                                                                 pb.e_orb ? pb.e_orb : de.get());
+                GSC_HIP(hipStreamSynchronize(st));
+            }
+            if (pb.stats) pb.stats->seconds = ms * 1e-3;
+        }
+        GSC_HIP(hipGetLastError());
+        GSC_HIP(hipStreamSynchronize(st));
+        return s;
+    });
 }
 
 }  // extern "C"

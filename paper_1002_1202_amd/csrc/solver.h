@@ -47,5 +47,10 @@ struct SolveRequest {
 };
 
 gsc_status run_solve(Ctx &ctx, SolveRequest &req);
+// Many projected-carry solves at once: one job per (system, rhs tile), each
+// iterating as a captured hipGraph of `graph_iters` outer iterations on one
+// of up to `max_streams` streams; iters[s] receives the iterations run.
+gsc_status run_batched(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_iters, int max_streams,
+                       std::vector<int> &iters);
 
 }  // namespace gsc

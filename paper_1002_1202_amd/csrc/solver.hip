@@ -17,6 +17,8 @@
 #include <algorithm>
 #include <array>
 #include <chrono>
+#include <memory>
+#include <thread>
 #include <cmath>
 #include <cstring>
 
@@ -510,7 +512,7 @@ __global__ void k_ritz_reduce(int Rp, const double *lmin, const double *lmax, do
 // Residual check of the Chebyshev iteration: a column is finished when
 // ||r - S y|| <= thr * ||r|| (inner_done = 1), else it needs more steps.
 __global__ __launch_bounds__(kBlock) void k_cheb_check(int Rp, int G, const double *partial, double thr,
-                                                       ColState cs) {
+                                                       int final_check, ColState cs) {
     __shared__ double lds[kBlock];
     const int c = blockIdx.x;
     if (cs.done[c] || cs.inner_done[c]) return;
@@ -519,7 +521,12 @@ __global__ __launch_bounds__(kBlock) void k_cheb_check(int Rp, int G, const doub
     const double rr = block_sum(v, lds);
     if (threadIdx.x != 0) return;
     if (!isfinite(rr)) { cs.flags[c] |= FLAG_NAN; cs.done[c] = 1; cs.inner_done[c] = 1; return; }
-    if (rr <= thr * thr * cs.rnorm2[c]) cs.inner_done[c] = 1;
+    if (rr <= thr * thr * cs.rnorm2[c]) {
+        cs.inner_done[c] = 1;
+    } else if (final_check) {
+        cs.flags[c] |= FLAG_INNER;   // inexact S^{-1} r for this column this iteration
+        cs.inner_done[c] = 1;
+    }
 }
 
 template <typename T>
@@ -1103,7 +1110,10 @@ template <typename T> class TileSolver {
     }
 
     // Runs the whole iteration; returns the number of outer iterations.
-    int run(const gsc_opts &o, double inner_tol, int seed0) {
+    // Everything before the first outer iteration: state, r = b, the first
+    // inner solve by CG (its coefficients give the Chebyshev interval),
+    // rho and p.  Synchronises the stream.
+    void init_phase(const gsc_opts &o, double inner_tol, int seed0) {
         auto &td = t_.td;
         ColState cs = t_.cols();
         ShiftState ss = t_.shifts(dz_);
@@ -1135,7 +1145,60 @@ template <typename T> class TileSolver {
                                          t_.P.get(), t_.ldk, nullptr);
         GSC_HIP(hipGetLastError());
         check_status(false);
+        (void)NR;
+    }
 
+    // One outer iteration of a projected-carry tile with no host
+    // synchronisation (graph-capturable: the kernels do not depend on n
+    // beyond the profiling histogram).
+    void enqueue_projected_iteration(const gsc_opts &o, int n) {
+        auto &td = t_.td;
+        ColState cs = t_.cols();
+        ShiftState ss = t_.shifts(dz_);
+        const dim3 eg(td.Rp / 64, td.G), eb(kBlock);
+        const T *Sv = sval(), *Hv = hval();
+        cpx<T> *rp = t_.ring.get();   // m = 1 for the projected carry
+        launch_spmm_seed<T>(st_, pr_, td, Sv, Hv, t_.p.get(), t_.q.get(), dz_, t_.c_seed.get(), t_.c_done.get(),
+                            t_.part_c.get());
+        k_ctrl<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.Gs, n, 0, t_.part_c.get(), cs, ss);
+        proj_update(cs, ss, 0, rp);
+        k_update_r<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_alpha.get(), t_.q.get(),
+                                         t_.r.get(), t_.res.get(), t_.d.get(), t_.part_d.get(), nullptr);
+        k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 0, inner_tol_, cs);
+        inner_solve_cheb(o, cs, rp);
+        k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), rp, t_.r.get(),
+                                        t_.part_c.get(), nullptr);
+        k_post<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.G, n, 0, t_.part_c.get(), o.tol, cs, ss, t_.h.get(),
+                                          t_.dh.get(), t_.Mu + t_.srow);
+        k_p_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, 0, cs, rp, t_.r.get(), t_.p.get(), t_.P.get(),
+                                         t_.ldk, nullptr);
+        GSC_HIP(hipGetLastError());
+    }
+
+    bool chebyshev_ready() const { return cheb_ok_; }
+    hipStream_t stream() const { return st_; }
+    void set_stream(hipStream_t s) { st_ = s; }
+    // enqueue the status reduction and its copy into host memory `h`
+    void enqueue_status(Status *d, Status *h) {
+        k_status<<<1, kBlock, 0, st_>>>(t_.td.Rp, t_.cols(), d);
+        GSC_HIP(hipGetLastError());
+        GSC_HIP(hipMemcpyAsync(h, d, sizeof(Status), hipMemcpyDeviceToHost, st_));
+    }
+    void note_status(const Status &s) {
+        flags_ |= s.flags;
+        if (s.flags & FLAG_NAN) throw Error(GSC_E_NAN, "non-finite value in the iteration");
+        if (s.flags & FLAG_NOT_SPD) throw Error(GSC_E_S_NOT_SPD, "inner CG found d^H S d <= 0: S is not positive definite");
+        if (s.flags & FLAG_BREAKDOWN) throw Error(GSC_E_BREAKDOWN, "COCG breakdown (p^T A p or r'^T r vanished)");
+    }
+
+    int run(const gsc_opts &o, double inner_tol, int seed0) {
+        init_phase(o, inner_tol, seed0);
+        auto &td = t_.td;
+        ColState cs = t_.cols();
+        ShiftState ss = t_.shifts(dz_);
+        const dim3 eg(td.Rp / 64, td.G), eb(kBlock);
+        const int cb = div_up(td.Rp, 256);
+        const size_t NR = static_cast<size_t>(td.N) * td.Rp;
         const T *Sv = sval(), *Hv = hval();
         int n0 = 0;   // first unflushed step (full carry)
         int n = 0;
@@ -1190,6 +1253,8 @@ template <typename T> class TileSolver {
         if (prof_.on) account_bytes(n);
         return n;
     }
+
+    int flags() const { return flags_; }
 
     void write_outputs(gsc_stats *stats, double *res_host, unsigned char *conv_host, double tol, int nrhs_total) {
         auto &td = t_.td;
@@ -1299,7 +1364,6 @@ template <typename T> class TileSolver {
     int switches() const { return switches_; }
     long long shift_rhs_iters() const { return shift_rhs_iters_; }
     double worst_res() const { return worst_res_; }
-    int flags() const { return flags_; }
 
   private:
     const T *sval() const;
@@ -1402,8 +1466,13 @@ template <typename T> class TileSolver {
         cheb_hi_ = h[1];
     }
 
-    // Chebyshev iteration for S y = r (r in t_.r), y_K written to `ytarget`.
+    // Chebyshev iteration for S y = r (r in t_.r), y_K written to `ytarget`,
+    // with no host synchronisation: K - 1 fused steps, a residual check of
+    // y_{K-1} at tol / rho, two more steps only for the columns that failed
+    // it (the parity brings their y_{K+2} back into `ytarget`), and a final
+    // check at tol that flags columns still above it.
     void inner_solve_cheb(const gsc_opts &o, ColState cs, cpx<T> *ytarget) {
+        (void)o;
         auto &td = t_.td;
         const T *Sv = sval();
         const double sigma = cheb_theta_ / cheb_delta_;
@@ -1412,36 +1481,23 @@ template <typename T> class TileSolver {
         buf[K % 2] = ytarget;
         buf[(K + 1) % 2] = t_.w.get();
         double rho_prev = 1.0 / sigma;
-        int k = 1;
-        auto step = [&](int kk) {
+        auto step = [&](int kk, const int *skip, double bytes) {
             const double rho = 1.0 / (2.0 * sigma - rho_prev);
             const double c1 = rho * rho_prev, c2 = 2.0 * rho / cheb_delta_;
-            prof_.begin(st_, KP_CHEB, static_cast<double>(last_active_) * td.N * sizeof(cpx<T>) * (kk == 1 ? 3 : 5));
+            prof_.begin(st_, KP_CHEB, bytes);
             launch_cheb_step<T>(st_, pr_, td, kk == 1, Sv, buf[kk % 2], t_.r.get(), t_.d.get(),
-                                buf[(kk + 1) % 2], t_.c_done.get(), 1.0 / cheb_theta_, c1, c2, t_.part_d.get());
+                                buf[(kk + 1) % 2], skip, 1.0 / cheb_theta_, c1, c2, t_.part_d.get());
             prof_.end(st_);
             rho_prev = rho;
         };
-        for (; k < K; ++k) step(k);
-        // residual of y_{K-1} (one step behind y_K): accept at tol / rho
-        k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_ / cheb_rho_, cs);
+        const double vec = static_cast<double>(last_active_) * td.N * sizeof(cpx<T>);
+        for (int k = 1; k < K; ++k) step(k, t_.c_done.get(), vec * (k == 1 ? 3 : 5));
+        k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_ / cheb_rho_, 0, cs);
+        step(K, t_.c_inner_done.get(), 0.0);
+        step(K + 1, t_.c_inner_done.get(), 0.0);
+        k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_, 1, cs);
         GSC_HIP(hipGetLastError());
-        Status s = check_status(false);
-        int extra = 0;
-        while (s.inner_pending > 0 && K + extra < o.inner_max_iter) {
-            step(k);
-            ++k;
-            ++extra;
-            k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_, cs);
-            s = check_status(false);
-        }
-        if (k % 2 != K % 2) {
-            const size_t n = static_cast<size_t>(td.N) * td.Rp;
-            k_copy_vec<T><<<div_up(static_cast<int64_t>(n), 256), 256, 0, st_>>>(n, buf[k % 2], ytarget);
-            GSC_HIP(hipGetLastError());
-        }
-        cheb_extra_ += extra;
-        inner_total_ += k - 1;
+        inner_total_ += K - 1;
     }
 
     void inner_solve_cg(const gsc_opts &o, ColState cs, cpx<T> *y) {
@@ -1641,7 +1697,7 @@ gsc_status solve_typed(Ctx &ctx, SolveRequest &req) {
         inner += ts.inner_total();
         switches += ts.switches();
         sri += ts.shift_rhs_iters();
-        if (ts.worst_res() > o.tol) all_conv = false;
+        if (ts.worst_res() > o.tol || (ts.flags() & FLAG_INNER)) all_conv = false;
     }
     GSC_HIP(hipEventRecord(e1, st));
     GSC_HIP(hipEventSynchronize(e1));
@@ -1660,7 +1716,172 @@ gsc_status solve_typed(Ctx &ctx, SolveRequest &req) {
     return all_conv ? GSC_OK : GSC_NOT_CONVERGED;
 }
 
+// ------------------------------------------------------------------ batched
+struct BatchJob {
+    SolveRequest *req = nullptr;
+    int sys = 0, r0 = 0, R = 0;
+    double work = 0.0;
+};
+
+template <typename T>
+gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_iters, int max_streams,
+                         std::vector<int> &iters_out) {
+    // jobs: one per (system, rhs tile), longest first
+    std::vector<BatchJob> jobs;
+    for (size_t si = 0; si < reqs.size(); ++si) {
+        SolveRequest &rq = reqs[si];
+        const int Rt = rq.opts.rhs_tile > 0 ? rq.opts.rhs_tile : rq.R;
+        for (int r0 = 0; r0 < rq.R; r0 += Rt) {
+            BatchJob j;
+            j.req = &rq;
+            j.sys = static_cast<int>(si);
+            j.r0 = r0;
+            j.R = std::min(Rt, rq.R - r0);
+            j.work = static_cast<double>(rq.pair->n) * j.R * (rq.K + 64.0);
+            jobs.push_back(j);
+        }
+    }
+    std::stable_sort(jobs.begin(), jobs.end(), [](const BatchJob &a, const BatchJob &b) { return a.work > b.work; });
+    const int ns = std::max(1, std::min<int>(max_streams, static_cast<int>(jobs.size())));
+    std::vector<hipStream_t> streams(ns);
+    for (auto &st : streams) GSC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    struct Live {
+        std::unique_ptr<TileSolver<T>> ts;
+        DevBuf<c128> dz;
+        DevBuf<int64_t> drhs;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipEvent_t ev = nullptr;
+        DevBuf<Status> dstat;
+        Status *hstat = nullptr;
+        int n = 0;
+        bool inflight = false, finished = false, graphed = false;
+        gsc_opts o{};
+    };
+    std::vector<Live> live(jobs.size());
+    const bool prof_was_on = ctx.prof.on;
+    ctx.prof.on = false;   // no event nodes inside captured graphs
+    gsc_status result = GSC_OK;
+    try {
+        for (size_t j = 0; j < jobs.size(); ++j) {
+            BatchJob &jb = jobs[j];
+            SolveRequest &rq = *jb.req;
+            Live &L = live[j];
+            L.o = rq.opts;
+            hipStream_t st = streams[j % ns];
+            std::vector<double> zh(rq.z, rq.z + 2 * rq.K);
+            L.dz.alloc(rq.K);
+            GSC_HIP(hipMemcpyAsync(L.dz.get(), zh.data(), zh.size() * sizeof(double), hipMemcpyHostToDevice, st));
+            const int Rp = (jb.R + 63) / 64 * 64;
+            std::vector<int64_t> h(Rp, 0);
+            for (int c = 0; c < jb.R; ++c) h[c] = rq.rhs_idx[jb.r0 + c];
+            L.drhs.alloc(Rp);
+            GSC_HIP(hipMemcpyAsync(L.drhs.get(), h.data(), Rp * sizeof(int64_t), hipMemcpyHostToDevice, st));
+            const int seed0 = L.o.seed_index >= 0 ? L.o.seed_index : default_seed(zh, rq.K);
+            const double inner_tol = L.o.inner_tol > 0 ? L.o.inner_tol : std::max(1e-2 * L.o.tol, 1e-15);
+            L.ts = std::make_unique<TileSolver<T>>(ctx, rq, L.dz.get(), L.drhs.get(), nullptr, jb.r0, jb.R, Rp, 1,
+                                                   false);
+            L.ts->set_stream(st);
+            L.ts->allocate();
+            L.ts->init_phase(L.o, inner_tol, seed0);
+            GSC_HIP(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
+            L.dstat.alloc(1);
+            GSC_HIP(hipHostMalloc(reinterpret_cast<void **>(&L.hstat), sizeof(Status), hipHostMallocDefault));
+            if (L.ts->chebyshev_ready() && L.o.inner_method != 1) {
+                // capture graph_iters outer iterations once; replay until done
+                GSC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                for (int g = 0; g < graph_iters; ++g) L.ts->enqueue_projected_iteration(L.o, 0);
+                GSC_HIP(hipStreamEndCapture(st, &L.graph));
+                GSC_HIP(hipGraphInstantiate(&L.exec, L.graph, nullptr, nullptr, 0));
+                L.graphed = true;
+            }
+        }
+        // scheduler: keep one chunk in flight per job, poll completion events
+        size_t remaining = jobs.size();
+        while (remaining > 0) {
+            bool progress = false;
+            for (size_t j = 0; j < jobs.size(); ++j) {
+                Live &L = live[j];
+                if (L.finished) continue;
+                hipStream_t st = streams[j % ns];
+                if (!L.inflight) {
+                    if (L.graphed) {
+                        GSC_HIP(hipGraphLaunch(L.exec, st));
+                        L.n += graph_iters;
+                    } else {
+                        L.ts->enqueue_projected_iteration(L.o, L.n);
+                        L.n += 1;
+                    }
+                    L.ts->enqueue_status(L.dstat.get(), L.hstat);
+                    GSC_HIP(hipEventRecord(L.ev, st));
+                    L.inflight = true;
+                    progress = true;
+                    continue;
+                }
+                const hipError_t q = hipEventQuery(L.ev);
+                if (q == hipErrorNotReady) continue;
+                GSC_HIP(q);
+                L.inflight = false;
+                progress = true;
+                const Status s = *L.hstat;
+                L.ts->note_status(s);
+                if (s.active_cols == 0 || L.n >= L.o.max_iter) {
+                    L.finished = true;
+                    --remaining;
+                }
+            }
+            if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+        for (auto &st : streams) GSC_HIP(hipStreamSynchronize(st));
+        iters_out.assign(reqs.size(), 0);
+        for (size_t j = 0; j < jobs.size(); ++j) {
+            Live &L = live[j];
+            SolveRequest &rq = *jobs[j].req;
+            double *res_host = rq.stats ? rq.stats->res_recursive : nullptr;
+            unsigned char *conv_host = rq.stats ? rq.stats->converged : nullptr;
+            L.ts->write_outputs(rq.stats, res_host, conv_host, L.o.tol, rq.R);
+            iters_out[jobs[j].sys] = std::max(iters_out[jobs[j].sys], std::min(L.n, L.o.max_iter));
+            if (rq.stats) {
+                rq.stats->outer_iters = iters_out[jobs[j].sys];
+                rq.stats->inner_iters += L.ts->inner_total();
+                rq.stats->shift_rhs_iters += L.ts->shift_rhs_iters();
+            }
+            if (L.ts->worst_res() > L.o.tol || (L.ts->flags() & FLAG_INNER)) result = GSC_NOT_CONVERGED;
+        }
+    } catch (...) {
+        ctx.prof.on = prof_was_on;
+        for (auto &L : live) {
+            if (L.exec) (void)hipGraphExecDestroy(L.exec);
+            if (L.graph) (void)hipGraphDestroy(L.graph);
+            if (L.ev) (void)hipEventDestroy(L.ev);
+            if (L.hstat) (void)hipHostFree(L.hstat);
+        }
+        for (auto &st : streams) { (void)hipStreamSynchronize(st); (void)hipStreamDestroy(st); }
+        throw;
+    }
+    ctx.prof.on = prof_was_on;
+    for (auto &L : live) {
+        if (L.exec) (void)hipGraphExecDestroy(L.exec);
+        if (L.graph) (void)hipGraphDestroy(L.graph);
+        if (L.ev) (void)hipEventDestroy(L.ev);
+        if (L.hstat) (void)hipHostFree(L.hstat);
+    }
+    for (auto &st : streams) (void)hipStreamDestroy(st);
+    return result;
+}
+
 }  // namespace
+
+gsc_status run_batched(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_iters, int max_streams,
+                       std::vector<int> &iters) {
+    bool mixed = false;
+    for (auto &r : reqs) mixed |= r.opts.precision == GSC_MIXED;
+    if (mixed) {
+        for (auto &r : reqs) ensure_f32(const_cast<Pair &>(*r.pair));
+        return batched_typed<float>(ctx, reqs, graph_iters, max_streams, iters);
+    }
+    return batched_typed<double>(ctx, reqs, graph_iters, max_streams, iters);
+}
 
 gsc_status run_solve(Ctx &ctx, SolveRequest &req) {
     if (req.opts.precision == GSC_MIXED) {
