@@ -52,6 +52,7 @@ def describe(cfg, args):
         "carry": "full",
         "fuse_steps": args.fuse,
         "spmm_kernel": args.spmm,
+        "inner_method": args.inner,
         "precision": args.precision,
         "parallelism": "1 GPU",
     }
@@ -81,6 +82,60 @@ def cpu_baseline(cfg, iters):
                       f"steps) in {dt:.1f} s"}
 
 
+def batched_compare(ctx):
+    """Mixed-precision batched solve vs the plain FP64 batched solve at tol
+    1e-6 on the 32-system workload (G_jj, charges, band-energy terms), with
+    the errors stated: mixed vs FP64 on every system, FP64 vs the dense-LU
+    oracle on sampled shifts of the two smallest systems."""
+    import numpy as np
+    import torch
+
+    from oracle import ased as oased, green as ogreen
+    from paper_1002_1202_amd import api
+    from synth import configs
+    from synth.grids import trapezoid_weights
+
+    b = configs.batch32()
+    probs = []
+    for it in b["items"]:
+        pair, _ = api.pair_from_system(ctx, it["system"])
+        probs.append(dict(pair=pair, z=it["z"], rhs=it["rhs"], w=trapezoid_weights(it["z"])))
+    out = {"workload": "batch32: 32 Si systems (N 3776..131072, K 147..1013, R 80..508), tol 1e-6"}
+    res = {}
+    for prec in ("mixed", "fp64"):
+        api.solve_batched(ctx, probs[:2], tol=1e-6, precision=prec, max_iter=4)   # warm the code paths
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = api.solve_batched(ctx, probs, tol=1e-6, precision=prec, graph_iters=4)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        work = sum(x["shift_rhs_iters"] for x in o)
+        res[prec] = o
+        out[prec] = {"seconds": dt, "value": work / dt, "unit": UNIT,
+                     "max_outer_iters": max(x["outer_iters"] for x in o),
+                     "converged_frac": float(np.mean([x["converged"].mean() for x in o]))}
+        print(f"batched {prec}: {dt:.2f} s, {work / dt:.3e} shift-rhs-it/s", file=sys.stderr, flush=True)
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    gm = max(float((x["G_jj"] - y["G_jj"]).abs().max() / y["G_jj"].abs().max())
+             for x, y in zip(res["mixed"], res["fp64"]))
+    qm = max(float((x["q"] - y["q"]).abs().max()) for x, y in zip(res["mixed"], res["fp64"]))
+    out["err_mixed_vs_fp64"] = {"G_jj_rel": gm, "charge_abs_e": qm}
+    # FP64 batched vs the dense-LU oracle on 4 sampled shifts of the 2 smallest systems
+    order = sorted(range(len(probs)), key=lambda i: probs[i]["pair"].n)[:2]
+    errs = []
+    for i in order:
+        it = b["items"][i]
+        S, H, _ = oased.dense_pair(it["system"])
+        ks = np.linspace(0, len(it["z"]) - 1, 4).astype(int)
+        X = ogreen.solve_dense(H, S, it["z"][ks], it["rhs"])
+        g0 = X[:, np.arange(len(it["rhs"])), it["rhs"]]
+        for prec in ("fp64", "mixed"):
+            g = res[prec][i]["G_jj"].cpu().numpy()[ks]
+            errs.append((prec, float(np.abs(g - g0).max() / np.abs(g0).max())))
+    out["err_vs_oracle_sampled"] = {p: max(e for q, e in errs if q == p) for p in ("fp64", "mixed")}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +148,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--spmm", type=int, default=0, help="0 auto, 1 row kernel, 2 cluster kernel")
+    ap.add_argument("--inner", type=int, default=0, help="0 auto, 1 CG, 2 Chebyshev")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="copy 1 GiB device-to-device first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no collectives, no sharding); "
@@ -104,6 +164,12 @@ def main():
 
     from paper_1002_1202_amd import api
 
+    if args.copy_probe:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        b = a.clone()
+        torch.cuda.synchronize()
+        print(f"copy probe: {a.numel() * 8} bytes read and written", file=sys.stderr, flush=True)
+        del a, b
     cfg = workload(args.workload)
     if args.tol is None:
         args.tol = cfg["tol"]
@@ -114,10 +180,20 @@ def main():
     pair = api.Pair(ctx, s.block, s.rowptr, s.colidx)
     Gc = torch.empty((K, R, N), dtype=torch.complex128, device="cuda:0")
 
+    knobs = dict(fuse_steps=args.fuse, spmm_kernel=args.spmm, inner_method=args.inner)
+    tuned = None
+    if not args.no_autotune:
+        from paper_1002_1202_amd import autotune
+        api.ased_build(ctx, pair, s)
+        tuned = autotune.tune_solve(ctx, pair, z, rhs, precision=args.precision, carry="full", tol=args.tol,
+                                    verbose=True, force=True)
+        knobs.update(tuned)
+        print(f"autotuned: {tuned}", file=sys.stderr, flush=True)
+
     def step():
         api.ased_build(ctx, pair, s)
         return api.solve(ctx, pair, z, rhs=rhs, out="device", out_cols=Gc, tol=args.tol,
-                         fuse_steps=args.fuse, precision=args.precision, spmm_kernel=args.spmm)
+                         precision=args.precision, **knobs)
 
     # warmup; the first warmup step times every kernel to find the dominant one
     dom = None
@@ -182,6 +258,12 @@ def main():
                      "avg_launch_ms": ms / max(launches, 1), "traffic": None},
         "kernels": kernels,
     }
+    line["config"].update({k: v for k, v in knobs.items()})
+    line["config"]["autotuned"] = tuned is not None
+    del Gc
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        line["batched"] = batched_compare(ctx)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters)
     print(json.dumps(line), flush=True)

@@ -84,8 +84,11 @@ typedef struct {
     int rhs_tile;          /* [0 = auto] right-hand sides per device tile      */
     int recheck;           /* [0] 1: FP64 true residual of every (k, rhs) into
                               gsc_stats.res_true (full carry only)             */
-    int spmm_kernel;       /* [0 = auto] 1: one block row per wave, 2: register-
-                              blocked clusters of block rows sharing x loads   */
+    int spmm_kernel;       /* [0 = auto = 1] product kernel layout: 1 one block
+                              row x 64 rhs per wave, 2 register-blocked
+                              clusters of block rows sharing x loads, 3 one
+                              block row x a 16-rhs slab per wave with each
+                              XCD sweeping its slabs in row order            */
     int inner_method;      /* [0 = auto] inner solver for S r' = r: 1 CG (the
                               first solve always runs CG), 2 Chebyshev on the
                               interval of the first CG solve's Ritz values

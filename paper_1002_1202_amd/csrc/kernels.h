@@ -71,6 +71,26 @@ __device__ inline void xcd_remap(int &cx, int &gy) {
     gy = lp / gx;
 }
 
+// XCD-aware map for the gathered products: XCD x (= linear id mod 8) owns
+// one column chunk (or a set of chunks) and walks its share of the row
+// groups in order, so the x rows a chunk needs (its rows plus the
+// neighbour halo) are fetched into one L2 instead of into all eight.
+__device__ inline void xcd_remap_chunks(int &cx, int &gy) {
+    const int gx = gridDim.x, G = gridDim.y;
+    const int l = blockIdx.x + gx * blockIdx.y;
+    const int x = l & 7, k = l >> 3;
+    if (gx <= 8 && (8 % gx) == 0) {
+        const int share = 8 / gx;
+        cx = x % gx;
+        gy = (x / gx) * (G / share) + k;
+    } else if ((gx % 8) == 0) {
+        cx = x + 8 * (k / G);
+        gy = k % G;
+    } else {
+        xcd_remap(cx, gy);
+    }
+}
+
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Algorithmic-byte counter of a launch (profiling only; ctr may be null):

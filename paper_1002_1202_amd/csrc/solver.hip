@@ -688,13 +688,21 @@ __global__ __launch_bounds__(kBlock) void k_flush(int N, int Rp, int K, int m, i
                                                   int kper, ColState cs, ShiftState ss,
                                                   const cpx<T> *__restrict__ ring, size_t ring_ld,
                                                   cpx<T> *__restrict__ X, size_t ldx, cpx<T> *__restrict__ P,
-                                                  size_t ldp) {
-    const int col = blockIdx.y;
+                                                  size_t ldp, int R) {
+    // XCD-aware order: the 8 columns that share each 128-byte line of the
+    // r' ring ([N][Rp] layout) are consecutive blocks of one XCD, so the
+    // strided ring reads of 7 of them hit in that XCD's L2.
+    const int nrc = gridDim.x;
+    const int l = blockIdx.x + nrc * blockIdx.y;
+    const int xq = l & 7, kk = l >> 3, sub = kk & 7, q = kk >> 3;
+    const int rc = q % nrc;
+    const int col = (xq + 8 * (q / nrc)) * 8 + sub;
+    if (col >= R) return;
     if (only_sw && cs.sw[col] != 1) return;
     const int tb = max(n0, cs.applied[col]);
     const int cnt = n1 - tb;
     if (cnt <= 0) return;
-    const int ibase = blockIdx.x * (kBlock * E) + threadIdx.x;
+    const int ibase = rc * (kBlock * E) + threadIdx.x;
     cpx<T> rr[M][E];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
@@ -1035,7 +1043,7 @@ template <typename T> class TileSolver {
         td.m = m;
         td.G = pick_groups(td.N, Rp / 64, 2048);
         td.Lr = div_up(td.N, td.G);
-        set_spmm_geometry(td, pr_, req.opts.spmm_kernel == 2 ? 1 : 0);
+        set_spmm_geometry(td, pr_, req.opts.spmm_kernel == 2 ? 1 : req.opts.spmm_kernel == 3 ? 2 : 0);
         st_ = ctx_.stream;
         if (ctx_.prof.on) {
             const int mi = std::max(1, req.opts.max_iter);
@@ -1539,12 +1547,12 @@ template <typename T> class TileSolver {
         if (prof_.on) flushes_.push_back({n0, n1, only_sw ? nsw : -1});
         constexpr int E = 2;
         const int kper = std::max(1, std::min(td.K, 64));
-        dim3 grid(div_up(td.N, kBlock * E), td.R, div_up(td.K, kper));
+        dim3 grid(div_up(td.N, kBlock * E), td.Rp, div_up(td.K, kper));
         const size_t NR = static_cast<size_t>(td.N) * td.Rp;
         prof_.begin(st_, KP_SHIFT_UPDATE, 0.0);
 #define GSC_FLUSH(MM)                                                                                        \
     k_flush<T, MM, E, 1><<<grid, kBlock, 0, st_>>>(td.N, td.Rp, td.K, td.m, n0, n1, only_sw, kper, cs, ss, \
-                                                   t_.ring.get(), NR, t_.X, ldk_x_, t_.P.get(), t_.ldk)
+                                                   t_.ring.get(), NR, t_.X, ldk_x_, t_.P.get(), t_.ldk, td.R)
         if (td.m <= 1) GSC_FLUSH(1);
         else if (td.m <= 2) GSC_FLUSH(2);
         else if (td.m <= 4) GSC_FLUSH(4);
@@ -1608,6 +1616,14 @@ template <> const double *TileSolver<double>::hval() const { return pr_.H.get();
 template <> const float *TileSolver<float>::sval() const { return pr_.S32.get(); }
 template <> const float *TileSolver<float>::hval() const { return pr_.H32.get(); }
 
+// Inner S-solve tolerance: 1e-2 tol by default, floored by what the vector
+// precision can reach (complex64 products cannot resolve residuals below a
+// few ulps of FP32; asking for more stalls the outer iteration).
+template <typename T> double default_inner_tol(const gsc_opts &o) {
+    const double floor_t = std::is_same<T, float>::value ? 2e-6 : 1e-15;
+    return o.inner_tol > 0 ? std::max(o.inner_tol, floor_t) : std::max(1e-2 * o.tol, floor_t);
+}
+
 int default_seed(const std::vector<double> &z, int K) {
     double lo = z[0], hi = z[0];
     for (int k = 0; k < K; ++k) { lo = std::min(lo, z[2 * k]); hi = std::max(hi, z[2 * k]); }
@@ -1629,7 +1645,7 @@ gsc_status solve_typed(Ctx &ctx, SolveRequest &req) {
     DevBuf<c128> dz(req.K);
     GSC_HIP(hipMemcpyAsync(dz.get(), zh.data(), zh.size() * sizeof(double), hipMemcpyHostToDevice, st));
     const int seed0 = o.seed_index >= 0 ? o.seed_index : default_seed(zh, req.K);
-    double inner_tol = o.inner_tol > 0 ? o.inner_tol : std::max(1e-2 * o.tol, 1e-15);
+    double inner_tol = default_inner_tol<T>(o);
 
     // tile width: all rhs if memory allows
     int Rt = o.rhs_tile > 0 ? o.rhs_tile : req.R;
@@ -1778,7 +1794,7 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
             L.drhs.alloc(Rp);
             GSC_HIP(hipMemcpyAsync(L.drhs.get(), h.data(), Rp * sizeof(int64_t), hipMemcpyHostToDevice, st));
             const int seed0 = L.o.seed_index >= 0 ? L.o.seed_index : default_seed(zh, rq.K);
-            const double inner_tol = L.o.inner_tol > 0 ? L.o.inner_tol : std::max(1e-2 * L.o.tol, 1e-15);
+            const double inner_tol = default_inner_tol<T>(L.o);
             L.ts = std::make_unique<TileSolver<T>>(ctx, rq, L.dz.get(), L.drhs.get(), nullptr, jb.r0, jb.R, Rp, 1,
                                                    false);
             L.ts->set_stream(st);

@@ -20,4 +20,17 @@ void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, bool f
                       const cpx<T> *y, const cpx<T> *r, cpx<T> *d, cpx<T> *ynext, const int *skip, double inv_theta,
                       double c1, double c2, double *partial);
 
+int slab_groups(int nb);
+template <typename T>
+void launch_spmm_seed_slab(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const T *Hv,
+                           const cpx<T> *p, cpx<T> *q, const c128 *z, const int *seed, const int *skip,
+                           c128 *partial);
+template <typename T>
+void launch_spmm_S_slab(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const cpx<T> *d, cpx<T> *w,
+                        const int *skip, double *partial);
+template <typename T>
+void launch_cheb_slab(hipStream_t st, const Pair &pr, const TileDims &td, bool first, const T *Sv, const cpx<T> *y,
+                      const cpx<T> *r, cpx<T> *d, cpx<T> *ynext, const int *skip, double inv_theta, double c1,
+                      double c2, double *partial);
+
 }  // namespace gsc

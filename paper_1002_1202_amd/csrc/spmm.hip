@@ -22,7 +22,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_seed(
     cpx<T> *__restrict__ q, const c128 *__restrict__ z, const int *__restrict__ seed,
     const int *__restrict__ skip, c128 *__restrict__ partial, unsigned long long *ctr) {
     int cx, g;
-    xcd_remap(cx, g);
+    xcd_remap_chunks(cx, g);
     const int lane = threadIdx.x & 63;
     const int w = wave_id();
     const int col = cx * 64 + lane;
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_S(
     const T *__restrict__ Sv, const cpx<T> *__restrict__ d, cpx<T> *__restrict__ wout,
     const int *__restrict__ skip, double *__restrict__ partial, unsigned long long *ctr) {
     int cx, g;
-    xcd_remap(cx, g);
+    xcd_remap_chunks(cx, g);
     const int lane = threadIdx.x & 63;
     const int wv = wave_id();
     const int col = cx * 64 + lane;
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
     cpx<T> *__restrict__ dvec, cpx<T> *__restrict__ ynext, const int *__restrict__ skip, T inv_theta, T c1,
     T c2, double *__restrict__ partial) {
     int cx, g;
-    xcd_remap(cx, g);
+    xcd_remap_chunks(cx, g);
     const int lane = threadIdx.x & 63;
     const int wv = wave_id();
     const int col = cx * 64 + lane;
@@ -390,6 +390,10 @@ template <typename T>
 void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, bool first, const T *Sv,
                       const cpx<T> *y, const cpx<T> *r, cpx<T> *d, cpx<T> *ynext, const int *skip, double inv_theta,
                       double c1, double c2, double *partial) {
+    if (td.variant == 2) {
+        launch_cheb_slab<T>(st, pr, td, first, Sv, y, r, d, ynext, skip, inv_theta, c1, c2, partial);
+        return;
+    }
     // the fused step uses the one-block-row-per-wave layout (td.Lb rows per group)
     dim3 grid(td.Rp / 64, td.Gs), block(kBlock);
     const T it = static_cast<T>(inv_theta), a = static_cast<T>(c1), b = static_cast<T>(c2);
@@ -414,6 +418,12 @@ template void launch_cheb_step<float>(hipStream_t, const Pair &, const TileDims 
 // partials uses td.Gs, so both variants launch exactly td.Gs row groups.
 void set_spmm_geometry(TileDims &td, const Pair &pr, int variant) {
     td.variant = variant;
+    if (variant == 2) {
+        // slab kernels: one block row per wave, 4 per workgroup
+        td.Gs = slab_groups(td.nb);
+        td.Lb = kWavesPerBlock;
+        return;
+    }
     if (variant == 1) {
         // one cluster per wave: 4 clusters per block of 4 waves
         td.Gs = (div_up(pr.cl.nc, kWavesPerBlock) + 7) / 8 * 8;
@@ -434,6 +444,10 @@ void launch_spmm_seed(hipStream_t st, const Pair &pr, const TileDims &td, const 
                       const cpx<T> *p, cpx<T> *q, const c128 *z, const int *seed, const int *skip,
                       c128 *partial, unsigned long long *ctr) {
     dim3 grid(td.Rp / 64, td.Gs), block(kBlock);
+    if (td.variant == 2) {
+        launch_spmm_seed_slab<T>(st, pr, td, Sv, Hv, p, q, z, seed, skip, partial);
+        return;
+    }
     if (td.variant == 1) {
         int gy, Lc;
         cluster_geometry(pr, td, gy, Lc);
@@ -461,6 +475,10 @@ template <typename T>
 void launch_spmm_S(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const cpx<T> *d,
                    cpx<T> *w, const int *skip, double *partial, unsigned long long *ctr) {
     dim3 grid(td.Rp / 64, td.Gs), block(kBlock);
+    if (td.variant == 2) {
+        launch_spmm_S_slab<T>(st, pr, td, Sv, d, w, skip, partial);
+        return;
+    }
     if (td.variant == 1) {
         int gy, Lc;
         cluster_geometry(pr, td, gy, Lc);

@@ -311,3 +311,24 @@ def test_chebyshev_projected_water(ctx):
     X = ogreen.solve_dense(H, S, c["z"], rhs)
     ref = np.take_along_axis(X, np.broadcast_to(proj[None], (X.shape[0],) + proj.shape), axis=2)
     assert rel(res.G_proj, ref) < 1e-10
+
+
+@pytest.mark.parametrize("carry", ["full", "projected"])
+def test_slab_kernel_water_and_si(ctx, si216, carry):
+    """The slab product layout (16 rhs per wave for B = 4, 10 for B = 6) with
+    a ragged tail of columns, both carries."""
+    from paper_1002_1202_amd import api
+    print(f"case: slab kernels carry={carry}", flush=True)
+    for c in (si216[0], configs.water_small(n_mol=40, n_rhs=23)):
+        s = c["system"]
+        S, H, _ = oased.dense_pair(s)
+        pair, _ = api.pair_from_system(ctx, s)
+        rhs = c["rhs"][:70]
+        X = ogreen.solve_dense(H, S, c["z"], rhs)
+        if carry == "full":
+            res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, spmm_kernel=3)
+            assert rel(res.G_cols, X) < 1e-10
+        else:
+            proj = rhs[:, None]
+            res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, spmm_kernel=3, carry="projected", proj=proj)
+            assert rel(res.G_proj[:, :, 0], X[:, np.arange(len(rhs)), rhs]) < 1e-10
