@@ -88,7 +88,11 @@ typedef struct {
                               row x 64 rhs per wave, 2 register-blocked
                               clusters of block rows sharing x loads, 3 one
                               block row x a 16-rhs slab per wave with each
-                              XCD sweeping its slabs in row order            */
+                              XCD sweeping its slabs in row order, 4 as 1
+                              except the Chebyshev step, which reads the
+                              vectors as interleaved reals in 32-rhs stripes,
+                              one XCD per stripe when there are 8 stripes
+                              (256 padded rhs)                               */
     int inner_method;      /* [0 = auto] inner solver for S r' = r: 1 CG (the
                               first solve always runs CG), 2 Chebyshev on the
                               interval of the first CG solve's Ritz values
@@ -97,7 +101,11 @@ typedef struct {
                               interval is positive, else 1                     */
     int graph_iters;       /* [0 = 4] gsc_solve_batched: outer iterations per
                               captured hipGraph launch (between status polls)  */
-    int reserved[5];
+    int stream_hint;       /* [0 = auto = 1] 1: the Chebyshev step's streamed
+                              vectors are loaded and stored with the default
+                              cache policy, 2: nontemporal (kept out of L2 so
+                              the gathered halo stays resident)               */
+    int reserved[4];
 } gsc_opts;
 
 /* Statistics.  The three arrays are caller-owned HOST arrays of
@@ -239,9 +247,9 @@ gsc_status gsc_band_energy_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, c
  * gsc_profile_enable(ctx, 1) resets the counters and turns timing on.
  * gsc_profile_read returns, for one kernel name ("spmm_seed", "spmm_S",
  * "shift_update", "cg_update", "cg_dir", "update_r", "rho_dot", "p_update",
- * "ctrl", "post", "proj_update", "cheb_step"), the summed device milliseconds, the
- * number of launches and the summed algorithmic bytes those launches must
- * move (the method's own reads and writes, no re-reads).  GSC_E_ARG for an
+ * "ctrl", "post", "proj_update", "cheb_step", "ring_transpose"), the summed
+ * device milliseconds, the number of launches and the summed algorithmic
+ * bytes those launches must move (the method's own reads and writes, no re-reads).  GSC_E_ARG for an
  * unknown name. */
 gsc_status gsc_profile_enable(gsc_ctx *ctx, int on);
 /* Restrict the event timing to one kernel name (NULL: time every kernel);

@@ -115,7 +115,8 @@ void validate_opts(const gsc_opts &o) {
     GSC_REQUIRE(o.precision == GSC_FP64 || o.precision == GSC_MIXED, "unknown precision");
     GSC_REQUIRE(o.carry == GSC_CARRY_FULL || o.carry == GSC_CARRY_PROJECTED, "unknown carry mode");
     GSC_REQUIRE(o.fuse_steps >= 0 && o.fuse_steps <= kMaxFuse, "fuse_steps must be in [0, 16]");
-    GSC_REQUIRE(o.spmm_kernel >= 0 && o.spmm_kernel <= 3, "spmm_kernel must be 0, 1, 2 or 3");
+    GSC_REQUIRE(o.spmm_kernel >= 0 && o.spmm_kernel <= 4, "spmm_kernel must be 0 .. 4");
+    GSC_REQUIRE(o.stream_hint >= 0 && o.stream_hint <= 2, "stream_hint must be 0, 1 or 2");
     GSC_REQUIRE(o.inner_method >= 0 && o.inner_method <= 2, "inner_method must be 0, 1 or 2");
 }
 

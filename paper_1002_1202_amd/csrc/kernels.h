@@ -42,12 +42,20 @@ struct ShiftState {
     c128 *omega;              // collinear-restart weights (projected carry)
     double *res;              // recursive residual estimate at freeze / exit
     int *last;                // last active step (kFrozenNever while active)
-    c128 *ra, *rb, *rc;       // [m][K][Rp] shift-update coefficients
+    c128 *ra, *rb, *rc;       // [Rp][K][m] shift-update coefficients (see coef_at)
     // z-derivative carry (null unless requested): d/dz_k of pi, of the
     // restart weight and of the three update coefficients
     c128 *dpi, *dpi_prev, *dpi_next, *domega;
     c128 *rda, *rdb, *rdc;
+    int cK = 0, cm = 1;       // shifts and ring depth of the coefficient arrays
 };
+
+// Coefficient slot of (shift k, column c, ring slot): the m steps of one
+// (column, shift) pair are contiguous, so the fused update fetches all of
+// them with one vector load.
+__host__ __device__ inline size_t coef_at(const ShiftState &ss, int k, int c, int slot) {
+    return (static_cast<size_t>(c) * ss.cK + k) * ss.cm + slot;
+}
 
 struct TileDims {
     int N, nb, B, K, R, Rp, m;
@@ -55,7 +63,9 @@ struct TileDims {
     int Lr;                   // rows per group (vector kernels)
     int Gs;                   // row groups of the SpMM kernels (multiple of 8)
     int Lb;                   // block rows per SpMM group
-    int variant = 1;          // SpMM kernel: 0 one block row per wave, 1 register-blocked clusters
+    int variant = 1;          // SpMM kernel: 0 one block row per wave, 1 register-blocked clusters,
+                              // 2 slabs, 3 interleaved-real stripes (Chebyshev step)
+    bool nt = false;          // streamed vectors of the Chebyshev step bypass L2 retention
 };
 
 // XCD-aware remap of the linear block id: blocks l = x + gx*y are dispatched
@@ -89,6 +99,31 @@ __device__ inline void xcd_remap_chunks(int &cx, int &gy) {
     } else {
         xcd_remap(cx, gy);
     }
+}
+
+// loads and stores of streamed (read-once / write-once) vector elements;
+// NT marks them nontemporal so they do not displace reused lines in L2
+template <typename T, bool NT>
+__device__ inline T ld_stream(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <typename T, bool NT>
+__device__ inline void st_stream(T v, T *p) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <typename T, bool NT>
+__device__ inline cpx<T> ld_cpx(const cpx<T> *p) {
+    const T *q = reinterpret_cast<const T *>(p);
+    return {ld_stream<T, NT>(q), ld_stream<T, NT>(q + 1)};
+}
+template <typename T, bool NT>
+__device__ inline void st_cpx(cpx<T> v, cpx<T> *p) {
+    T *q = reinterpret_cast<T *>(p);
+    st_stream<T, NT>(v.re, q);
+    st_stream<T, NT>(v.im, q + 1);
 }
 
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }

@@ -245,7 +245,6 @@ __global__ __launch_bounds__(kBlock) void k_ctrl(int K, int Rp, int G, int n, in
     __syncthreads();
     if (!s_ok) return;
     const c128 alpha = s_alpha, tail = s_tail, zs = s_zs;
-    const size_t KR = static_cast<size_t>(K) * Rp;
     long long cnt = 0;
     for (int k = threadIdx.x; k < K; k += kBlock) {
         const size_t idx = static_cast<size_t>(k) * Rp + c;
@@ -258,9 +257,9 @@ __global__ __launch_bounds__(kBlock) void k_ctrl(int K, int Rp, int G, int n, in
         ss.pi_next[idx] = pin;
         const c128 q = cdiv(pim, pi);
         const c128 ak = cdiv(alpha * pi, pin);      // alpha^k_n
-        ss.ra[slot * KR + idx] = cdiv(c128{1.0, 0.0}, pi);
-        ss.rb[slot * KR + idx] = (q * q) * cs.beta_prev[c];
-        ss.rc[slot * KR + idx] = ss.omega[idx] * ak;
+        ss.ra[coef_at(ss, k, c, slot)] = cdiv(c128{1.0, 0.0}, pi);
+        ss.rb[coef_at(ss, k, c, slot)] = (q * q) * cs.beta_prev[c];
+        ss.rc[coef_at(ss, k, c, slot)] = ss.omega[idx] * ak;
         if (ss.dpi != nullptr) {
             // d/dz_k of the recurrence at a fixed seed process (delta' = 1)
             const c128 dpi = ss.dpi[idx], dpim = ss.dpi_prev[idx];
@@ -268,9 +267,9 @@ __global__ __launch_bounds__(kBlock) void k_ctrl(int K, int Rp, int G, int n, in
             ss.dpi_next[idx] = dpin;
             const c128 dak = cdiv(alpha * (dpi * pin - pi * dpin), pin * pin);
             const c128 dbk = cdiv(2.0 * cs.beta_prev[c] * q * (dpim * pi - pim * dpi), pi * pi);
-            ss.rda[slot * KR + idx] = cdiv(c128{-dpi.re, -dpi.im}, pi * pi);
-            ss.rdb[slot * KR + idx] = dbk;
-            ss.rdc[slot * KR + idx] = ss.domega[idx] * ak + ss.omega[idx] * dak;
+            ss.rda[coef_at(ss, k, c, slot)] = cdiv(c128{-dpi.re, -dpi.im}, pi * pi);
+            ss.rdb[coef_at(ss, k, c, slot)] = dbk;
+            ss.rdc[coef_at(ss, k, c, slot)] = ss.domega[idx] * ak + ss.omega[idx] * dak;
         }
     }
     s_cnt[threadIdx.x] = cnt;
@@ -673,36 +672,119 @@ __global__ __launch_bounds__(kBlock) void k_p_update(int N, int Rp, int Lr, int 
     }
 }
 
+// Column-major copy of one r' ring slot: dst[c][i] = src[i][c].  The fused
+// shift update walks one column's rows, which this layout makes contiguous.
+// Tile of 32 rows x 64 columns through LDS (row stride padded by one).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_ring_transpose(int N, int Rp, const cpx<T> *__restrict__ src,
+                                                           cpx<T> *__restrict__ dst) {
+    __shared__ cpx<T> tile[64][33];
+    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 32;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int c = t & 63, r = (t >> 6) + 4 * j;
+        if (r0 + r < N) tile[c][r] = src[static_cast<size_t>(r0 + r) * Rp + c0 + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int r = t & 31, c = (t >> 5) + 8 * j;
+        if (r0 + r < N) dst[static_cast<size_t>(c0 + c) * N + r0 + r] = tile[c][r];
+    }
+}
+
 __global__ void k_mark_applied(int Rp, int n1, ColState cs) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c < Rp && cs.sw[c] == 1) cs.applied[c] = n1;
 }
 
 // ------------------------------------------------------------------ fused shift update
+__device__ inline double readlane_f64(double v, int l) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffull), l));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(u >> 32), l));
+    return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+__device__ inline c128 readlane_c128(c128 v, int l) { return {readlane_f64(v.re, l), readlane_f64(v.im, l)}; }
+
+// The update coefficients of steps [tb, tb + M) of shift k, column col, one
+// per lane: lane w*M + j holds coefficient w (0: a, 1: b, 2: c) of step
+// tb + j.  One vector load per shift (contiguous [Rp][K][m] layout).
+template <int M>
+__device__ inline c128 load_coefs(const ShiftState &ss, int k, int col, int tb, int cnt, int m) {
+    const int lane = threadIdx.x & 63;
+    const int w = lane / M, j = lane % M;
+    if (w >= 3 || j >= cnt) return {0, 0};
+    const c128 *arr = w == 0 ? ss.ra : w == 1 ? ss.rb : ss.rc;
+    return arr[coef_at(ss, k, col, (tb + j) % m)];
+}
+
+// Walks the shifts of one column that still take steps in a pass, 64 at a
+// time: lane l holds the step count of shift q*64 + l, and a ballot gives
+// the active ones, so frozen shifts cost nothing.
+struct ActiveShifts {
+    int K, Rp, col, tb, n1, q = -1, st = 0;
+    unsigned long long mask = 0;
+    const int *last;
+    // next active shift (k, its step count) or k = -1
+    __device__ inline void next(int &k, int &kc) {
+        while (mask == 0) {
+            if ((q + 1) * 64 >= K) { k = -1; kc = 0; return; }
+            ++q;
+            const int kk = q * 64 + static_cast<int>(threadIdx.x & 63);
+            st = 0;
+            if (kk < K) {
+                const int l = last[static_cast<size_t>(kk) * Rp + col];
+                st = (l >= n1 ? n1 : l + 1) - tb;
+            }
+            mask = __ballot(st > 0);
+        }
+        const int b = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        k = q * 64 + b;
+        kc = __builtin_amdgcn_readlane(st, b);
+    }
+};
+
 // Applies the pending steps t in [max(n0, applied[c]), n1) of the shifted
 // recurrences to x^k, p^k of column c:  p <- a_t r'_t + b_t p;  x <- x + c_t p,
-// skipping steps after a shift froze.  r'_t stays in registers across all
-// shifts of the block; x^k, p^k are read and written once per pass.
-template <typename T, int M, int E, int KU>
+// skipping shifts that froze before the pass and steps after a shift froze.
+// r'_t stays in registers across all shifts of the column (read from the
+// column-major copy of the ring); x^k, p^k are read and written once per
+// pass.  The next active shift's rows and coefficients are in flight while
+// the current one is updated.
+template <typename T, int M, int E>
 __global__ __launch_bounds__(kBlock) void k_flush(int N, int Rp, int K, int m, int n0, int n1, int only_sw,
-                                                  int kper, ColState cs, ShiftState ss,
-                                                  const cpx<T> *__restrict__ ring, size_t ring_ld,
+                                                  ColState cs, ShiftState ss,
+                                                  const cpx<T> *__restrict__ ringT, size_t ring_ld,
                                                   cpx<T> *__restrict__ X, size_t ldx, cpx<T> *__restrict__ P,
                                                   size_t ldp, int R) {
-    // XCD-aware order: the 8 columns that share each 128-byte line of the
-    // r' ring ([N][Rp] layout) are consecutive blocks of one XCD, so the
-    // strided ring reads of 7 of them hit in that XCD's L2.
-    const int nrc = gridDim.x;
-    const int l = blockIdx.x + nrc * blockIdx.y;
-    const int xq = l & 7, kk = l >> 3, sub = kk & 7, q = kk >> 3;
-    const int rc = q % nrc;
-    const int col = (xq + 8 * (q / nrc)) * 8 + sub;
+    const int rc = blockIdx.x;
+    const int col = blockIdx.y;
     if (col >= R) return;
     if (only_sw && cs.sw[col] != 1) return;
     const int tb = max(n0, cs.applied[col]);
     const int cnt = n1 - tb;
     if (cnt <= 0) return;
+    ActiveShifts act{K, Rp, col, tb, n1};
+    act.last = ss.last;
+    int k, kc;
+    act.next(k, kc);
+    if (k < 0) return;
     const int ibase = rc * (kBlock * E) + threadIdx.x;
+    const size_t base = static_cast<size_t>(col) * N;
+    auto load_rows = [&](int kk, cpx<T> (&pv)[E], cpx<T> (&xv)[E]) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = ibase + e * kBlock;
+            pv[e] = i < N ? P[static_cast<size_t>(kk) * ldp + base + i] : cpx<T>{0, 0};
+            xv[e] = i < N ? X[static_cast<size_t>(kk) * ldx + base + i] : cpx<T>{0, 0};
+        }
+    };
+    cpx<T> pv[E], xv[E];
+    load_rows(k, pv, xv);
+    c128 cf = load_coefs<M>(ss, k, col, tb, cnt, m);
     cpx<T> rr[M][E];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
@@ -710,61 +792,46 @@ __global__ __launch_bounds__(kBlock) void k_flush(int N, int Rp, int K, int m, i
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int i = ibase + e * kBlock;
-            rr[j][e] = (j < cnt && i < N) ? ring[slot * ring_ld + static_cast<size_t>(i) * Rp + col]
+            rr[j][e] = (j < cnt && i < N) ? ringT[slot * ring_ld + static_cast<size_t>(col) * N + i]
                                           : cpx<T>{0, 0};
         }
     }
-    const size_t KR = static_cast<size_t>(K) * Rp;
-    const int k0 = blockIdx.z * kper;
-    const int k1 = min(K, k0 + kper);
-    for (int k = k0; k < k1; k += KU) {
-        // KU shifts in flight: loads of all of them are issued before the math
-        int kc[KU];
-        cpx<T> pv[KU][E], xv[KU][E];
-#pragma unroll
-        for (int u = 0; u < KU; ++u) {
-            kc[u] = 0;
-            if (k + u < k1) {
-                const int last = ss.last[static_cast<size_t>(k + u) * Rp + col];
-                kc[u] = (last >= n1 ? n1 : last + 1) - tb;
-            }
-            const size_t base = static_cast<size_t>(col) * N;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int i = ibase + e * kBlock;
-                const bool ok = kc[u] > 0 && i < N;
-                pv[u][e] = ok ? P[static_cast<size_t>(k + u) * ldp + base + i] : cpx<T>{0, 0};
-                xv[u][e] = ok ? X[static_cast<size_t>(k + u) * ldx + base + i] : cpx<T>{0, 0};
-            }
+    while (k >= 0) {
+        int kn, kcn;
+        act.next(kn, kcn);
+        cpx<T> pn[E], xn[E];
+        c128 cfn{0, 0};
+        if (kn >= 0) {
+            load_rows(kn, pn, xn);
+            cfn = load_coefs<M>(ss, kn, col, tb, cnt, m);
         }
 #pragma unroll
         for (int j = 0; j < M; ++j) {
+            if (j < kc) {
+                const cpx<T> a = ccast<T>(readlane_c128(cf, j));
+                const cpx<T> b = ccast<T>(readlane_c128(cf, M + j));
+                const cpx<T> cc = ccast<T>(readlane_c128(cf, 2 * M + j));
 #pragma unroll
-            for (int u = 0; u < KU; ++u) {
-                if (j < kc[u]) {
-                    const size_t sidx = static_cast<size_t>((tb + j) % m) * KR + static_cast<size_t>(k + u) * Rp + col;
-                    const cpx<T> a = ccast<T>(ss.ra[sidx]), b = ccast<T>(ss.rb[sidx]), cc = ccast<T>(ss.rc[sidx]);
-#pragma unroll
-                    for (int e = 0; e < E; ++e) {
-                        pv[u][e] = a * rr[j][e] + b * pv[u][e];
-                        xv[u][e] = xv[u][e] + cc * pv[u][e];
-                    }
+                for (int e = 0; e < E; ++e) {
+                    pv[e] = a * rr[j][e] + b * pv[e];
+                    xv[e] = xv[e] + cc * pv[e];
                 }
             }
         }
 #pragma unroll
-        for (int u = 0; u < KU; ++u) {
-            if (kc[u] <= 0) continue;
-            const size_t base = static_cast<size_t>(col) * N;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int i = ibase + e * kBlock;
-                if (i < N) {
-                    P[static_cast<size_t>(k + u) * ldp + base + i] = pv[u][e];
-                    X[static_cast<size_t>(k + u) * ldx + base + i] = xv[u][e];
-                }
+        for (int e = 0; e < E; ++e) {
+            const int i = ibase + e * kBlock;
+            if (i < N) {
+                P[static_cast<size_t>(k) * ldp + base + i] = pv[e];
+                X[static_cast<size_t>(k) * ldx + base + i] = xv[e];
             }
         }
+        if (kn < 0) break;
+#pragma unroll
+        for (int e = 0; e < E; ++e) { pv[e] = pn[e]; xv[e] = xn[e]; }
+        cf = cfn;
+        k = kn;
+        kc = kcn;
     }
 }
 
@@ -798,12 +865,11 @@ __global__ __launch_bounds__(kBlock) void k_proj_update(int K, int Rp, int Mu, i
         if (threadIdx.x == 0) cr[Mu] = tot;
     }
     __syncthreads();
-    const size_t KR = static_cast<size_t>(K) * Rp;
     for (int t = threadIdx.x; t < K * M; t += kBlock) {
         const int k = t / M, m = t % M;
         const size_t idx = static_cast<size_t>(k) * Rp + c;
         if (ss.last[idx] != kFrozenNever) continue;
-        const size_t s = static_cast<size_t>(slot) * KR + idx;
+        const size_t s = coef_at(ss, k, c, slot);
         const size_t o = idx * M + m;
         const c128 hv = ss.ra[s] * cr[m] + ss.rb[s] * h[o];
         h[o] = hv;
@@ -843,14 +909,13 @@ __global__ __launch_bounds__(kBlock) void k_proj_update_vjp(
         if (threadIdx.x == 0) cr[Mu] = tot;
     }
     __syncthreads();
-    const size_t KR = static_cast<size_t>(K) * Rp;
     for (int m = threadIdx.x; m < M; m += kBlock) {
         const c128 crm = cr[m];
         c128 ag{0, 0}, ad{0, 0}, az{0, 0};
         for (int k = 0; k < K; ++k) {
             const size_t idx = static_cast<size_t>(k) * Rp + c;
             if (ss.last[idx] != kFrozenNever) continue;
-            const size_t sidx = static_cast<size_t>(slot) * KR + idx;
+            const size_t sidx = coef_at(ss, k, c, slot);
             const size_t o = idx * M + m;
             const c128 hold = h[o], dhold = dh[o];
             const c128 hv = ss.ra[sidx] * crm + ss.rb[sidx] * hold;
@@ -968,7 +1033,7 @@ int pick_groups(int64_t rows, int colchunks, int target_blocks) {
 
 template <typename T> struct Tile {
     TileDims td{};
-    DevBuf<cpx<T>> p, q, r, res, d, w, ring;
+    DevBuf<cpx<T>> p, q, r, res, d, w, ring, ringT;
     DevBuf<cpx<T>> Xown, P;
     cpx<T> *X = nullptr;
     size_t ldk = 0;
@@ -1010,6 +1075,7 @@ template <typename T> struct Tile {
         s.z = z; s.pi = s_pi.get(); s.pi_prev = s_pi_prev.get(); s.pi_next = s_pi_next.get();
         s.omega = s_omega.get(); s.res = s_res.get(); s.last = s_last.get();
         s.ra = s_ra.get(); s.rb = s_rb.get(); s.rc = s_rc.get();
+        s.cK = td.K; s.cm = td.m;
         s.dpi = s_dpi.get(); s.dpi_prev = s_dpi_prev.get(); s.dpi_next = s_dpi_next.get();
         s.domega = s_domega.get(); s.rda = s_rda.get(); s.rdb = s_rdb.get(); s.rdc = s_rdc.get();
         return s;
@@ -1043,7 +1109,11 @@ template <typename T> class TileSolver {
         td.m = m;
         td.G = pick_groups(td.N, Rp / 64, 2048);
         td.Lr = div_up(td.N, td.G);
-        set_spmm_geometry(td, pr_, req.opts.spmm_kernel == 2 ? 1 : req.opts.spmm_kernel == 3 ? 2 : 0);
+        {
+            const int k = req.opts.spmm_kernel;
+            set_spmm_geometry(td, pr_, k == 2 ? 1 : k == 3 ? 2 : k == 4 ? 3 : 0);
+            td.nt = req.opts.stream_hint == 2;
+        }
         st_ = ctx_.stream;
         if (ctx_.prof.on) {
             const int mi = std::max(1, req.opts.max_iter);
@@ -1059,6 +1129,7 @@ template <typename T> class TileSolver {
         const size_t NR = static_cast<size_t>(td.N) * td.Rp;
         t_.p.alloc(NR); t_.q.alloc(NR); t_.r.alloc(NR); t_.res.alloc(NR); t_.d.alloc(NR); t_.w.alloc(NR);
         t_.ring.alloc(NR * td.m);
+        if (full_) t_.ringT.alloc(NR * td.m);
         const size_t Rp = td.Rp;
         t_.c_rho.alloc(Rp); t_.c_alpha.alloc(Rp); t_.c_alpha_prev.alloc(Rp); t_.c_beta_prev.alloc(Rp);
         t_.c_swc.alloc(Rp); t_.c_swcm.alloc(Rp);
@@ -1145,6 +1216,10 @@ template <typename T> class TileSolver {
         k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 1, inner_tol, cs);
         inner_tol_ = inner_tol;
         inner_solve_cg(o, cs, t_.ring.get());
+        if (full_) {
+            k_ring_transpose<T><<<dim3(td.Rp / 64, div_up(td.N, 32)), kBlock, 0, st_>>>(td.N, td.Rp, t_.ring.get(),
+                                                                                      t_.ringT.get());
+        }
         if (o.inner_method != 1) setup_chebyshev(o, inner_tol);
         k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), t_.ring.get(),
                                         t_.r.get(), t_.part_c.get(), nullptr);
@@ -1254,6 +1329,13 @@ template <typename T> class TileSolver {
             k_p_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, 0, cs, rp_next, t_.r.get(), t_.p.get(),
                                              t_.P.get(), t_.ldk, ctr(KP_P_UPDATE));
             prof_.end(st_);
+            if (full_) {
+                // after the switch rescale of r' in k_p_update
+                prof_.begin(st_, KP_RING_T, 0.0);
+                k_ring_transpose<T><<<dim3(td.Rp / 64, div_up(td.N, 32)), kBlock, 0, st_>>>(
+                    td.N, td.Rp, rp_next, t_.ringT.get() + slot_next * NR);
+                prof_.end(st_);
+            }
             if (s.active_cols == 0) { ++n; break; }
         }
         if (full_ && n > n0) flush(cs, ss, n0, n, 0);
@@ -1403,6 +1485,7 @@ template <typename T> class TileSolver {
         prof_.add_bytes(KP_UPDATE_R, s_it * vec * 5);
         prof_.add_bytes(KP_RHO_DOT, solves * vec * 2);
         prof_.add_bytes(KP_P_UPDATE, solves * vec * 3);
+        if (full_) prof_.add_bytes(KP_RING_T, solves * vec * 2);
         prof_.add_bytes(KP_SPMM_S, s_in * vec * 2);
         prof_.add_bytes(KP_CG_UPDATE, (6 * s_in - solves) * vec);
         prof_.add_bytes(KP_CG_DIR, 3 * (s_in - solves) * vec);
@@ -1545,14 +1628,13 @@ template <typename T> class TileSolver {
     void flush(ColState cs, ShiftState ss, int n0, int n1, int only_sw, int nsw = -1) {
         auto &td = t_.td;
         if (prof_.on) flushes_.push_back({n0, n1, only_sw ? nsw : -1});
-        constexpr int E = 2;
-        const int kper = std::max(1, std::min(td.K, 64));
-        dim3 grid(div_up(td.N, kBlock * E), td.Rp, div_up(td.K, kper));
+        constexpr int E = 1;
+        dim3 grid(div_up(td.N, kBlock * E), td.Rp, 1);
         const size_t NR = static_cast<size_t>(td.N) * td.Rp;
         prof_.begin(st_, KP_SHIFT_UPDATE, 0.0);
 #define GSC_FLUSH(MM)                                                                                        \
-    k_flush<T, MM, E, 1><<<grid, kBlock, 0, st_>>>(td.N, td.Rp, td.K, td.m, n0, n1, only_sw, kper, cs, ss, \
-                                                   t_.ring.get(), NR, t_.X, ldk_x_, t_.P.get(), t_.ldk, td.R)
+    k_flush<T, MM, E><<<grid, kBlock, 0, st_>>>(td.N, td.Rp, td.K, td.m, n0, n1, only_sw, cs, ss, \
+                                                   t_.ringT.get(), NR, t_.X, ldk_x_, t_.P.get(), t_.ldk, td.R)
         if (td.m <= 1) GSC_FLUSH(1);
         else if (td.m <= 2) GSC_FLUSH(2);
         else if (td.m <= 4) GSC_FLUSH(4);

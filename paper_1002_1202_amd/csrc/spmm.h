@@ -3,7 +3,9 @@
 
 namespace gsc {
 
-// variant 0: one block row per wave; 1: register-blocked clusters
+// variant 0: one block row per wave; 1: register-blocked clusters; 2: slabs;
+// 3: interleaved-real stripes of 32 columns for the Chebyshev step (the other
+// products use the variant-0 kernels on the same row groups)
 void set_spmm_geometry(TileDims &td, const Pair &pr, int variant);
 
 template <typename T>
@@ -19,6 +21,11 @@ template <typename T>
 void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, bool first, const T *Sv,
                       const cpx<T> *y, const cpx<T> *r, cpx<T> *d, cpx<T> *ynext, const int *skip, double inv_theta,
                       double c1, double c2, double *partial);
+
+template <typename T>
+void launch_cheb_il(hipStream_t st, const Pair &pr, const TileDims &td, bool first, const T *Sv, const cpx<T> *y,
+                    const cpx<T> *r, cpx<T> *d, cpx<T> *ynext, const int *skip, double inv_theta, double c1,
+                    double c2, double *partial);
 
 int slab_groups(int nb);
 template <typename T>

@@ -308,7 +308,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_S_cl(
 //   res_k = r - S y_k,  d_k = c1 d_{k-1} + c2 res_k,  y_{k+1} = y_k + d_k.
 // FIRST: y_1 = r / theta and d_0 = r / theta are formed on the fly from r.
 // One gathered vector (y_k, or r when FIRST) and a partial ||res_k||^2.
-template <typename T, int B, bool FIRST>
+template <typename T, int B, bool FIRST, bool NT>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(
     int nb, int Rp, int Lb, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const T *__restrict__ Sv, const cpx<T> *__restrict__ y, const cpx<T> *__restrict__ r,
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
             for (int a = 0; a < B; ++a) {
                 const size_t e = static_cast<size_t>(I * B + a) * Rp + col;
                 cpx<T> yk, dprev;
-                const cpx<T> rv = FIRST ? own[a] : r[e];
+                const cpx<T> rv = FIRST ? own[a] : ld_cpx<T, NT>(r + e);
                 cpx<T> Sy = aS[a];
                 if (FIRST) {
                     yk = inv_theta * own[a];
@@ -365,12 +365,12 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
                     Sy = inv_theta * Sy;
                 } else {
                     yk = own[a];
-                    dprev = dvec[e];
+                    dprev = ld_cpx<T, NT>(dvec + e);
                 }
                 const cpx<T> res = rv - Sy;
                 const cpx<T> dn = c1 * dprev + c2 * res;
-                dvec[e] = dn;
-                ynext[e] = yk + dn;
+                st_cpx<T, NT>(dn, dvec + e);
+                st_cpx<T, NT>(yk + dn, ynext + e);
                 acc2 += static_cast<double>(res.re) * res.re + static_cast<double>(res.im) * res.im;
             }
         }
@@ -394,14 +394,21 @@ void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, bool f
         launch_cheb_slab<T>(st, pr, td, first, Sv, y, r, d, ynext, skip, inv_theta, c1, c2, partial);
         return;
     }
+    if (td.variant == 3) {
+        launch_cheb_il<T>(st, pr, td, first, Sv, y, r, d, ynext, skip, inv_theta, c1, c2, partial);
+        return;
+    }
     // the fused step uses the one-block-row-per-wave layout (td.Lb rows per group)
     dim3 grid(td.Rp / 64, td.Gs), block(kBlock);
     const T it = static_cast<T>(inv_theta), a = static_cast<T>(c1), b = static_cast<T>(c2);
-#define GSC_CHEB(BB, F)                                                                                      \
-    k_cheb_step<T, BB, F><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(), Sv, \
-                                                  y, r, d, ynext, skip, it, a, b, partial)
-    if (pr.B == 4) { if (first) GSC_CHEB(4, true); else GSC_CHEB(4, false); }
-    else { if (first) GSC_CHEB(6, true); else GSC_CHEB(6, false); }
+#define GSC_CHEB(BB, F, N)                                                                                      \
+    k_cheb_step<T, BB, F, N><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(), Sv, \
+                                                     y, r, d, ynext, skip, it, a, b, partial)
+#define GSC_CHEB_B(BB)                                                                  \
+    if (first) { if (td.nt) GSC_CHEB(BB, true, true); else GSC_CHEB(BB, true, false); } \
+    else { if (td.nt) GSC_CHEB(BB, false, true); else GSC_CHEB(BB, false, false); }
+    if (pr.B == 4) { GSC_CHEB_B(4) } else { GSC_CHEB_B(6) }
+#undef GSC_CHEB_B
 #undef GSC_CHEB
     GSC_HIP(hipGetLastError());
 }
@@ -427,6 +434,11 @@ void set_spmm_geometry(TileDims &td, const Pair &pr, int variant) {
     if (variant == 1) {
         // one cluster per wave: 4 clusters per block of 4 waves
         td.Gs = (div_up(pr.cl.nc, kWavesPerBlock) + 7) / 8 * 8;
+    } else if (variant == 3) {
+        // 32-column stripes: about 16k waves over the stripes and row groups
+        int g = std::max(1, 4096 / std::max(1, td.Rp / 32));
+        g = static_cast<int>(std::min<int64_t>(g, (td.nb + 3) / 4));
+        td.Gs = (std::max(g, 1) + 7) / 8 * 8;
     } else {
         int g = std::max(1, 2048 / std::max(1, td.Rp / 64));
         g = static_cast<int>(std::min<int64_t>(g, (td.nb + 3) / 4));
