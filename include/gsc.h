@@ -89,10 +89,11 @@ typedef struct {
                               clusters of block rows sharing x loads, 3 one
                               block row x a 16-rhs slab per wave with each
                               XCD sweeping its slabs in row order, 4 as 1
-                              except the Chebyshev step, which reads the
-                              vectors as interleaved reals in 32-rhs stripes,
-                              one XCD per stripe when there are 8 stripes
-                              (256 padded rhs)                               */
+                              except the Chebyshev step, which takes one
+                              block row x 32 rhs per wave (each half-wave
+                              half of the block's orbitals), one XCD per
+                              32-rhs stripe when there are 8 stripes (256
+                              padded rhs)                                     */
     int inner_method;      /* [0 = auto] inner solver for S r' = r: 1 CG (the
                               first solve always runs CG), 2 Chebyshev on the
                               interval of the first CG solve's Ritz values

@@ -64,7 +64,7 @@ struct TileDims {
     int Gs;                   // row groups of the SpMM kernels (multiple of 8)
     int Lb;                   // block rows per SpMM group
     int variant = 1;          // SpMM kernel: 0 one block row per wave, 1 register-blocked clusters,
-                              // 2 slabs, 3 interleaved-real stripes (Chebyshev step)
+                              // 2 slabs, 3 split-orbital 32-column stripes (Chebyshev step)
     bool nt = false;          // streamed vectors of the Chebyshev step bypass L2 retention
 };
 
@@ -124,6 +124,33 @@ __device__ inline void st_cpx(cpx<T> v, cpx<T> *p) {
     T *q = reinterpret_cast<T *>(p);
     st_stream<T, NT>(v.re, q);
     st_stream<T, NT>(v.im, q + 1);
+}
+
+// Three-term Chebyshev update of one element of S y = r:
+//   res = r - S y_k,   y_{k+1} = y_k + c1 (y_k - y_{k-1}) + c2 res,
+// written over y_{k-1} (yio).  own = y_k at this element (taken from the
+// gathered diagonal block), Sx = the gathered product.  MODE 0: the first
+// step, whose gathered vector is r and y_1 = r / theta, y_0 = 0; MODE 1:
+// y_{k-1} = y_1 = r / theta is formed from r; MODE 2: y_{k-1} is read.
+// Returns |res|^2.
+template <typename T, int MODE, bool NT>
+__device__ inline double cheb_update(cpx<T> own, cpx<T> Sx, const cpx<T> *__restrict__ r, cpx<T> *__restrict__ yio,
+                                     size_t e, T inv_theta, T c1, T c2) {
+    cpx<T> yk, rv, yprev, Sy = Sx;
+    if constexpr (MODE == 0) {
+        rv = own;
+        yk = inv_theta * own;
+        Sy = inv_theta * Sx;
+        yprev = {0, 0};
+    } else {
+        rv = ld_cpx<T, NT>(r + e);
+        yk = own;
+        if constexpr (MODE == 1) yprev = inv_theta * rv;
+        else yprev = ld_cpx<T, NT>(yio + e);
+    }
+    const cpx<T> res = rv - Sy;
+    st_cpx<T, NT>(yk + c1 * (yk - yprev) + c2 * res, yio + e);
+    return static_cast<double>(res.re) * res.re + static_cast<double>(res.im) * res.im;
 }
 
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }

@@ -1561,7 +1561,9 @@ template <typename T> class TileSolver {
     // with no host synchronisation: K - 1 fused steps, a residual check of
     // y_{K-1} at tol / rho, two more steps only for the columns that failed
     // it (the parity brings their y_{K+2} back into `ytarget`), and a final
-    // check at tol that flags columns still above it.
+    // check at tol that flags columns still above it.  Three-term form:
+    // step k reads y_k (gathered) and y_{k-1} and writes y_{k+1} over y_{k-1},
+    // so two buffers alternate.
     void inner_solve_cheb(const gsc_opts &o, ColState cs, cpx<T> *ytarget) {
         (void)o;
         auto &td = t_.td;
@@ -1576,13 +1578,13 @@ template <typename T> class TileSolver {
             const double rho = 1.0 / (2.0 * sigma - rho_prev);
             const double c1 = rho * rho_prev, c2 = 2.0 * rho / cheb_delta_;
             prof_.begin(st_, KP_CHEB, bytes);
-            launch_cheb_step<T>(st_, pr_, td, kk == 1, Sv, buf[kk % 2], t_.r.get(), t_.d.get(),
+            launch_cheb_step<T>(st_, pr_, td, kk == 1 ? 0 : kk == 2 ? 1 : 2, Sv, buf[kk % 2], t_.r.get(),
                                 buf[(kk + 1) % 2], skip, 1.0 / cheb_theta_, c1, c2, t_.part_d.get());
             prof_.end(st_);
             rho_prev = rho;
         };
         const double vec = static_cast<double>(last_active_) * td.N * sizeof(cpx<T>);
-        for (int k = 1; k < K; ++k) step(k, t_.c_done.get(), vec * (k == 1 ? 3 : 5));
+        for (int k = 1; k < K; ++k) step(k, t_.c_done.get(), vec * (k == 1 ? 2 : k == 2 ? 3 : 4));
         k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_ / cheb_rho_, 0, cs);
         step(K, t_.c_inner_done.get(), 0.0);
         step(K + 1, t_.c_inner_done.get(), 0.0);

@@ -4,7 +4,7 @@
 namespace gsc {
 
 // variant 0: one block row per wave; 1: register-blocked clusters; 2: slabs;
-// 3: interleaved-real stripes of 32 columns for the Chebyshev step (the other
+// 3: split-orbital stripes of 32 columns for the Chebyshev step (the other
 // products use the variant-0 kernels on the same row groups)
 void set_spmm_geometry(TileDims &td, const Pair &pr, int variant);
 
@@ -18,14 +18,14 @@ void launch_spmm_S(hipStream_t st, const Pair &pr, const TileDims &td, const T *
                    cpx<T> *w, const int *skip, double *partial, unsigned long long *ctr = nullptr);
 
 template <typename T>
-void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, bool first, const T *Sv,
-                      const cpx<T> *y, const cpx<T> *r, cpx<T> *d, cpx<T> *ynext, const int *skip, double inv_theta,
+void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, int mode, const T *Sv,
+                      const cpx<T> *y, const cpx<T> *r, cpx<T> *yio, const int *skip, double inv_theta,
                       double c1, double c2, double *partial);
 
 template <typename T>
-void launch_cheb_il(hipStream_t st, const Pair &pr, const TileDims &td, bool first, const T *Sv, const cpx<T> *y,
-                    const cpx<T> *r, cpx<T> *d, cpx<T> *ynext, const int *skip, double inv_theta, double c1,
-                    double c2, double *partial);
+void launch_cheb_split(hipStream_t st, const Pair &pr, const TileDims &td, int mode, const T *Sv, const cpx<T> *y,
+                       const cpx<T> *r, cpx<T> *yio, const int *skip, double inv_theta, double c1, double c2,
+                       double *partial);
 
 int slab_groups(int nb);
 template <typename T>
@@ -36,8 +36,8 @@ template <typename T>
 void launch_spmm_S_slab(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const cpx<T> *d, cpx<T> *w,
                         const int *skip, double *partial);
 template <typename T>
-void launch_cheb_slab(hipStream_t st, const Pair &pr, const TileDims &td, bool first, const T *Sv, const cpx<T> *y,
-                      const cpx<T> *r, cpx<T> *d, cpx<T> *ynext, const int *skip, double inv_theta, double c1,
-                      double c2, double *partial);
+void launch_cheb_slab(hipStream_t st, const Pair &pr, const TileDims &td, int mode, const T *Sv, const cpx<T> *y,
+                      const cpx<T> *r, cpx<T> *yio, const int *skip, double inv_theta, double c1, double c2,
+                      double *partial);
 
 }  // namespace gsc

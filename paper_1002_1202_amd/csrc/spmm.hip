@@ -304,16 +304,16 @@ __global__ __launch_bounds__(kBlock) void k_spmm_S_cl(
 
 // ------------------------------------------------------------------ Chebyshev step
 // One step of the Chebyshev iteration for S y = r on the interval
-// [theta - delta, theta + delta] fused with the product:
-//   res_k = r - S y_k,  d_k = c1 d_{k-1} + c2 res_k,  y_{k+1} = y_k + d_k.
-// FIRST: y_1 = r / theta and d_0 = r / theta are formed on the fly from r.
-// One gathered vector (y_k, or r when FIRST) and a partial ||res_k||^2.
-template <typename T, int B, bool FIRST, bool NT>
+// [theta - delta, theta + delta] fused with the product, in the three-term
+// form (see cheb_update): one gathered vector (y_k, or r in the first
+// step), r and y_{k-1} streamed, y_{k+1} written over y_{k-1}, and a
+// partial ||r - S y_k||^2.
+template <typename T, int B, int MODE, bool NT>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(
     int nb, int Rp, int Lb, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const T *__restrict__ Sv, const cpx<T> *__restrict__ y, const cpx<T> *__restrict__ r,
-    cpx<T> *__restrict__ dvec, cpx<T> *__restrict__ ynext, const int *__restrict__ skip, T inv_theta, T c1,
-    T c2, double *__restrict__ partial) {
+    cpx<T> *__restrict__ yio, const int *__restrict__ skip, T inv_theta, T c1, T c2,
+    double *__restrict__ partial) {
     int cx, g;
     xcd_remap_chunks(cx, g);
     const int lane = threadIdx.x & 63;
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
     double acc2 = 0.0;
     const int I0 = g * Lb;
     const int I1 = min(nb, I0 + Lb);
-    const cpx<T> *x = FIRST ? r : y;
+    const cpx<T> *x = MODE == 0 ? r : y;
     if (__ballot(act) != 0) {
         for (int I = I0 + wv; I < I1; I += kWavesPerBlock) {
             cpx<T> aS[B], own[B];
@@ -354,25 +354,9 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
             }
             if (!act) continue;
 #pragma unroll
-            for (int a = 0; a < B; ++a) {
-                const size_t e = static_cast<size_t>(I * B + a) * Rp + col;
-                cpx<T> yk, dprev;
-                const cpx<T> rv = FIRST ? own[a] : ld_cpx<T, NT>(r + e);
-                cpx<T> Sy = aS[a];
-                if (FIRST) {
-                    yk = inv_theta * own[a];
-                    dprev = yk;
-                    Sy = inv_theta * Sy;
-                } else {
-                    yk = own[a];
-                    dprev = ld_cpx<T, NT>(dvec + e);
-                }
-                const cpx<T> res = rv - Sy;
-                const cpx<T> dn = c1 * dprev + c2 * res;
-                st_cpx<T, NT>(dn, dvec + e);
-                st_cpx<T, NT>(yk + dn, ynext + e);
-                acc2 += static_cast<double>(res.re) * res.re + static_cast<double>(res.im) * res.im;
-            }
+            for (int a = 0; a < B; ++a)
+                acc2 += cheb_update<T, MODE, NT>(own[a], aS[a], r, yio, static_cast<size_t>(I * B + a) * Rp + col,
+                                                 inv_theta, c1, c2);
         }
     }
     __shared__ double red[kWavesPerBlock][64];
@@ -387,38 +371,39 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
 }
 
 template <typename T>
-void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, bool first, const T *Sv,
-                      const cpx<T> *y, const cpx<T> *r, cpx<T> *d, cpx<T> *ynext, const int *skip, double inv_theta,
+void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, int mode, const T *Sv,
+                      const cpx<T> *y, const cpx<T> *r, cpx<T> *yio, const int *skip, double inv_theta,
                       double c1, double c2, double *partial) {
     if (td.variant == 2) {
-        launch_cheb_slab<T>(st, pr, td, first, Sv, y, r, d, ynext, skip, inv_theta, c1, c2, partial);
+        launch_cheb_slab<T>(st, pr, td, mode, Sv, y, r, yio, skip, inv_theta, c1, c2, partial);
         return;
     }
     if (td.variant == 3) {
-        launch_cheb_il<T>(st, pr, td, first, Sv, y, r, d, ynext, skip, inv_theta, c1, c2, partial);
+        launch_cheb_split<T>(st, pr, td, mode, Sv, y, r, yio, skip, inv_theta, c1, c2, partial);
         return;
     }
     // the fused step uses the one-block-row-per-wave layout (td.Lb rows per group)
     dim3 grid(td.Rp / 64, td.Gs), block(kBlock);
     const T it = static_cast<T>(inv_theta), a = static_cast<T>(c1), b = static_cast<T>(c2);
-#define GSC_CHEB(BB, F, N)                                                                                      \
-    k_cheb_step<T, BB, F, N><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(), Sv, \
-                                                     y, r, d, ynext, skip, it, a, b, partial)
-#define GSC_CHEB_B(BB)                                                                  \
-    if (first) { if (td.nt) GSC_CHEB(BB, true, true); else GSC_CHEB(BB, true, false); } \
-    else { if (td.nt) GSC_CHEB(BB, false, true); else GSC_CHEB(BB, false, false); }
+#define GSC_CHEB(BB, M, N)                                                                                      \
+    k_cheb_step<T, BB, M, N><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(), Sv, \
+                                                     y, r, yio, skip, it, a, b, partial)
+#define GSC_CHEB_N(BB, M) \
+    if (td.nt) GSC_CHEB(BB, M, true); else GSC_CHEB(BB, M, false);
+#define GSC_CHEB_B(BB) \
+    if (mode == 0) { GSC_CHEB_N(BB, 0) } else if (mode == 1) { GSC_CHEB_N(BB, 1) } else { GSC_CHEB_N(BB, 2) }
     if (pr.B == 4) { GSC_CHEB_B(4) } else { GSC_CHEB_B(6) }
 #undef GSC_CHEB_B
+#undef GSC_CHEB_N
 #undef GSC_CHEB
     GSC_HIP(hipGetLastError());
 }
 
-template void launch_cheb_step<double>(hipStream_t, const Pair &, const TileDims &, bool, const double *,
-                                       const c128 *, const c128 *, c128 *, c128 *, const int *, double, double,
-                                       double, double *);
-template void launch_cheb_step<float>(hipStream_t, const Pair &, const TileDims &, bool, const float *,
-                                      const c64 *, const c64 *, c64 *, c64 *, const int *, double, double,
-                                      double, double *);
+template void launch_cheb_step<double>(hipStream_t, const Pair &, const TileDims &, int, const double *,
+                                       const c128 *, const c128 *, c128 *, const int *, double, double, double,
+                                       double *);
+template void launch_cheb_step<float>(hipStream_t, const Pair &, const TileDims &, int, const float *, const c64 *,
+                                      const c64 *, c64 *, const int *, double, double, double, double *);
 
 // ------------------------------------------------------------------ launchers
 // Row-group geometry of the product kernels.  Every reduction of their
@@ -440,7 +425,9 @@ void set_spmm_geometry(TileDims &td, const Pair &pr, int variant) {
         g = static_cast<int>(std::min<int64_t>(g, (td.nb + 3) / 4));
         td.Gs = (std::max(g, 1) + 7) / 8 * 8;
     } else {
-        int g = std::max(1, 2048 / std::max(1, td.Rp / 64));
+        // one block row per wave where the rows allow: the rows a sweep
+        // keeps in flight then span few x-planes, whose halo fits L2
+        int g = std::max(1, 4096 / std::max(1, td.Rp / 64));
         g = static_cast<int>(std::min<int64_t>(g, (td.nb + 3) / 4));
         td.Gs = (std::max(g, 1) + 7) / 8 * 8;
     }

@@ -136,11 +136,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_S_slab(
 }
 
 // Chebyshev step fused with the product (see k_cheb_step)
-template <typename T, int B, bool FIRST>
+template <typename T, int B, int MODE>
 __global__ __launch_bounds__(kBlock) void k_cheb_slab(
     int nb, int Rp, int G, int nsl, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const T *__restrict__ Sv, const cpx<T> *__restrict__ y, const cpx<T> *__restrict__ r,
-    cpx<T> *__restrict__ dvec, cpx<T> *__restrict__ ynext, const int *__restrict__ skip, T inv_theta, T c1, T c2,
+    cpx<T> *__restrict__ yio, const int *__restrict__ skip, T inv_theta, T c1, T c2,
     double *__restrict__ partial) {
     constexpr int CW = Slab<B>::CW;
     int slab, g;
@@ -153,25 +153,10 @@ __global__ __launch_bounds__(kBlock) void k_cheb_slab(
     double acc2 = 0.0;
     if (__ballot(act) != 0) {
         cpx<T> aS{0, 0}, unused{0, 0}, own{0, 0};
-        slab_row<T, B, false>(rowptr, colidx, Sv, Sv, FIRST ? r : y, I, a, Rp, col, act, aS, unused, own);
-        if (act) {
-            const size_t e = static_cast<size_t>(I * B + a) * Rp + col;
-            cpx<T> yk, dprev, Sy = aS;
-            const cpx<T> rv = FIRST ? own : r[e];
-            if (FIRST) {
-                yk = inv_theta * own;
-                dprev = yk;
-                Sy = inv_theta * Sy;
-            } else {
-                yk = own;
-                dprev = dvec[e];
-            }
-            const cpx<T> res = rv - Sy;
-            const cpx<T> dn = c1 * dprev + c2 * res;
-            dvec[e] = dn;
-            ynext[e] = yk + dn;
-            acc2 = static_cast<double>(res.re) * res.re + static_cast<double>(res.im) * res.im;
-        }
+        slab_row<T, B, false>(rowptr, colidx, Sv, Sv, MODE == 0 ? r : y, I, a, Rp, col, act, aS, unused, own);
+        if (act)
+            acc2 = cheb_update<T, MODE, false>(own, aS, r, yio, static_cast<size_t>(I * B + a) * Rp + col, inv_theta,
+                                               c1, c2);
     }
     slab_partial<double, CW>(acc2, partial, g, Rp, slab);
 }
@@ -216,17 +201,19 @@ void launch_spmm_S_slab(hipStream_t st, const Pair &pr, const TileDims &td, cons
 }
 
 template <typename T>
-void launch_cheb_slab(hipStream_t st, const Pair &pr, const TileDims &td, bool first, const T *Sv, const cpx<T> *y,
-                      const cpx<T> *r, cpx<T> *d, cpx<T> *ynext, const int *skip, double inv_theta, double c1,
-                      double c2, double *partial) {
+void launch_cheb_slab(hipStream_t st, const Pair &pr, const TileDims &td, int mode, const T *Sv, const cpx<T> *y,
+                      const cpx<T> *r, cpx<T> *yio, const int *skip, double inv_theta, double c1, double c2,
+                      double *partial) {
     const dim3 grid = slab_grid(pr.B, td.Rp, td.Gs);
     const int nsl = pr.B == 4 ? (td.Rp + 15) / 16 : (td.Rp + 9) / 10;
     const T it = static_cast<T>(inv_theta), a = static_cast<T>(c1), b = static_cast<T>(c2);
-#define GSC_CS(BB, F)                                                                                           \
-    k_cheb_slab<T, BB, F><<<grid, kBlock, 0, st>>>(td.nb, td.Rp, td.Gs, nsl, pr.rowptr.get(), pr.colidx.get(), Sv, \
-                                                   y, r, d, ynext, skip, it, a, b, partial)
-    if (pr.B == 4) { if (first) GSC_CS(4, true); else GSC_CS(4, false); }
-    else { if (first) GSC_CS(6, true); else GSC_CS(6, false); }
+#define GSC_CS(BB, M)                                                                                           \
+    k_cheb_slab<T, BB, M><<<grid, kBlock, 0, st>>>(td.nb, td.Rp, td.Gs, nsl, pr.rowptr.get(), pr.colidx.get(), Sv, \
+                                                   y, r, yio, skip, it, a, b, partial)
+#define GSC_CS_B(BB) \
+    if (mode == 0) GSC_CS(BB, 0); else if (mode == 1) GSC_CS(BB, 1); else GSC_CS(BB, 2);
+    if (pr.B == 4) { GSC_CS_B(4) } else { GSC_CS_B(6) }
+#undef GSC_CS_B
 #undef GSC_CS
     GSC_HIP(hipGetLastError());
 }
@@ -236,8 +223,8 @@ void launch_cheb_slab(hipStream_t st, const Pair &pr, const TileDims &td, bool f
                                            const cpx<T> *, cpx<T> *, const c128 *, const int *, const int *, c128 *); \
     template void launch_spmm_S_slab<T>(hipStream_t, const Pair &, const TileDims &, const T *, const cpx<T> *,     \
                                         cpx<T> *, const int *, double *);                                           \
-    template void launch_cheb_slab<T>(hipStream_t, const Pair &, const TileDims &, bool, const T *, const cpx<T> *, \
-                                      const cpx<T> *, cpx<T> *, cpx<T> *, const int *, double, double, double, double *);
+    template void launch_cheb_slab<T>(hipStream_t, const Pair &, const TileDims &, int, const T *, const cpx<T> *, \
+                                      const cpx<T> *, cpx<T> *, const int *, double, double, double, double *);
 GSC_INST(double)
 GSC_INST(float)
 #undef GSC_INST

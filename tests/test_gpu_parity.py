@@ -335,12 +335,13 @@ def test_slab_kernel_water_and_si(ctx, si216, carry):
 
 
 @pytest.mark.parametrize("hint", [1, 2])
-def test_interleaved_chebyshev_kernel(ctx, si216, hint):
-    """The Chebyshev step on interleaved-real 32-column stripes (both cache
-    policies for the streamed vectors), B = 4 and B = 6, a ragged column
-    tail (70 rhs -> 2 tiles of 64), FP64 and complex64 products."""
+def test_split_chebyshev_kernel(ctx, si216, hint):
+    """The Chebyshev step on 32-column stripes with the block's orbitals split
+    over the two half-waves (both cache policies for the streamed vectors),
+    B = 4 and B = 6, a ragged column tail (70 rhs -> 2 tiles of 64), FP64
+    and complex64 products."""
     from paper_1002_1202_amd import api
-    print(f"case: interleaved chebyshev stream_hint={hint}", flush=True)
+    print(f"case: split chebyshev stream_hint={hint}", flush=True)
     for c in (si216[0], configs.water_small(n_mol=40, n_rhs=23)):
         s = c["system"]
         S, H, _ = oased.dense_pair(s)
