@@ -142,17 +142,20 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="si4096")
-    ap.add_argument("--fuse", type=int, default=8)
+    ap.add_argument("--fuse", type=int, default=16)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=60)
-    ap.add_argument("--spmm", type=int, default=0, help="0 auto, 1 row kernel, 2 cluster kernel")
+    ap.add_argument("--spmm", type=int, default=0,
+                    help="0 auto, 1 row kernel, 2 cluster, 3 slab, 4 split-orbital Chebyshev")
     ap.add_argument("--inner", type=int, default=0, help="0 auto, 1 CG, 2 Chebyshev")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate launch shapes on this problem first and use the fastest")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="copy 1 GiB device-to-device first (calibrates HBM byte counters)")
+                    help="run a copy-like kernel over 1 GiB first (torch.neg: 1 GiB read, 1 GiB written), "
+                         "which calibrates the HBM byte counters of a --pmc run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no collectives, no sharding); "
@@ -165,8 +168,9 @@ def main():
     from paper_1002_1202_amd import api
 
     if args.copy_probe:
-        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
-        b = a.clone()
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.neg(a, out=b)
         torch.cuda.synchronize()
         print(f"copy probe: {a.numel() * 8} bytes read and written", file=sys.stderr, flush=True)
         del a, b
@@ -182,7 +186,7 @@ def main():
 
     knobs = dict(fuse_steps=args.fuse, spmm_kernel=args.spmm, inner_method=args.inner)
     tuned = None
-    if not args.no_autotune:
+    if args.autotune:
         from paper_1002_1202_amd import autotune
         api.ased_build(ctx, pair, s)
         tuned = autotune.tune_solve(ctx, pair, z, rhs, precision=args.precision, carry="full", tol=args.tol,
@@ -230,6 +234,11 @@ def main():
     total_bytes = sum(v[2] for v in prof.values())
     ms, launches, byts = prof[dom]
     achieved = (byts / (ms * 1e-3)) / 1e9 if ms > 0 else 0.0
+    from paper_1002_1202_amd import rocprof_summary
+    traffic = None
+    if dom in rocprof_summary.KERNEL_SOURCES and args.precision == "fp64":
+        traffic = rocprof_summary.read_traffic(
+            os.path.join(ROOT, "profiles", f"{cfg['name']}_{dom}_traffic.md"), dom)
     kernels = {k: {"warmup_ms": round(v[0], 3), "launches": v[1], "GB": round(v[2] / 1e9, 3),
                    "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
                for k, v in pw.items() if v[1] > 0}
@@ -255,7 +264,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "bytes_per_launch": byts / max(launches, 1),
-                     "avg_launch_ms": ms / max(launches, 1), "traffic": None},
+                     "avg_launch_ms": ms / max(launches, 1), "traffic": traffic},
         "kernels": kernels,
     }
     line["config"].update({k: v for k, v in knobs.items()})
