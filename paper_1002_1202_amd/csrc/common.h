@@ -103,17 +103,25 @@ struct Profiler {
     int only = -1;      // time only this kernel id (-1: all)
     struct Acc { double ms = 0; long long launches = 0; double bytes = 0; };
     Acc acc[KP_COUNT];
-    struct Pending { int id; hipEvent_t a, b; double bytes; };
+    struct Pending { int id; hipEvent_t a, b; double bytes; long long launches; };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
     hipEvent_t get_event();
-    void begin(hipStream_t st, int id, double bytes);
-    void end(hipStream_t st);
+    // one launch of kernel id between begin and end
+    void begin(hipStream_t st, int id, double bytes) { begin_group(st, id); end_pending_ = {bytes, 1}; }
+    void end(hipStream_t st) { end_group(st, end_pending_.launches, end_pending_.bytes); }
+    // `launches` back-to-back launches of kernel id between begin_group and
+    // end_group, timed by one event pair (their average includes the gaps
+    // between them)
+    void begin_group(hipStream_t st, int id);
+    void end_group(hipStream_t st, long long launches, double bytes);
     void resolve();     // call after the stream was synchronised
     void add_bytes(int id, double bytes) { acc[id].bytes += bytes; }
     void reset();
     ~Profiler();
     bool open_ = false;
+    int open_id_ = -1;
+    struct { double bytes; long long launches; } end_pending_{0.0, 1};
 };
 
 // ------------------------------------------------------------------ handles

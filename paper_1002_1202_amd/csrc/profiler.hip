@@ -22,22 +22,28 @@ hipEvent_t Profiler::get_event() {
     return e;
 }
 
-void Profiler::begin(hipStream_t st, int id, double bytes) {
-    if (!on) return;
-    if (only >= 0 && id != only) {
-        acc[id].bytes += bytes;
-        acc[id].launches += 1;
-        return;
-    }
-    Pending p{id, get_event(), get_event(), bytes};
+void Profiler::begin_group(hipStream_t st, int id) {
+    open_id_ = id;
+    if (!on || (only >= 0 && id != only)) return;
+    Pending p{id, get_event(), get_event(), 0.0, 0};
     GSC_HIP(hipEventRecord(p.a, st));
     pending.push_back(p);
     open_ = true;
 }
 
-void Profiler::end(hipStream_t st) {
-    if (!on || pending.empty() || open_ == false) return;
+void Profiler::end_group(hipStream_t st, long long launches, double bytes) {
+    if (!on) return;
+    if (!open_) {
+        // kernel not timed: count its launches and bytes only
+        if (open_id_ >= 0) {
+            acc[open_id_].launches += launches;
+            acc[open_id_].bytes += bytes;
+        }
+        return;
+    }
     GSC_HIP(hipEventRecord(pending.back().b, st));
+    pending.back().launches = launches;
+    pending.back().bytes = bytes;
     open_ = false;
 }
 
@@ -46,7 +52,7 @@ void Profiler::resolve() {
         float ms = 0.f;
         GSC_HIP(hipEventElapsedTime(&ms, p.a, p.b));
         acc[p.id].ms += ms;
-        acc[p.id].launches += 1;
+        acc[p.id].launches += p.launches;
         acc[p.id].bytes += p.bytes;
         pool.push_back(p.a);
         pool.push_back(p.b);

@@ -1466,10 +1466,8 @@ template <typename T> class TileSolver {
     void account_bytes(int n_iters) {
         auto &td = t_.td;
         std::vector<int> it(td.Rp);
-        std::vector<long long> inner(td.Rp), act(std::max(1, n_iters)), cols(std::max(1, n_iters));
+        std::vector<long long> act(std::max(1, n_iters)), cols(std::max(1, n_iters));
         GSC_HIP(hipMemcpyAsync(it.data(), t_.c_iters.get(), td.Rp * sizeof(int), hipMemcpyDeviceToHost, st_));
-        GSC_HIP(hipMemcpyAsync(inner.data(), t_.c_inner_total.get(), td.Rp * sizeof(long long),
-                               hipMemcpyDeviceToHost, st_));
         if (n_iters > 0) {
             GSC_HIP(hipMemcpyAsync(act.data(), t_.act_hist.get(), n_iters * sizeof(long long),
                                    hipMemcpyDeviceToHost, st_));
@@ -1477,8 +1475,8 @@ template <typename T> class TileSolver {
                                    hipMemcpyDeviceToHost, st_));
         }
         GSC_HIP(hipStreamSynchronize(st_));
-        double s_it = 0, s_in = 0;
-        for (int c = 0; c < td.R; ++c) { s_it += it[c]; s_in += inner[c]; }
+        double s_it = 0;
+        for (int c = 0; c < td.R; ++c) s_it += it[c];
         const double solves = s_it + td.R;
         const double vec = static_cast<double>(td.N) * sizeof(cpx<T>);
         prof_.add_bytes(KP_SPMM_SEED, s_it * vec * 2);
@@ -1486,9 +1484,6 @@ template <typename T> class TileSolver {
         prof_.add_bytes(KP_RHO_DOT, solves * vec * 2);
         prof_.add_bytes(KP_P_UPDATE, solves * vec * 3);
         if (full_) prof_.add_bytes(KP_RING_T, solves * vec * 2);
-        prof_.add_bytes(KP_SPMM_S, s_in * vec * 2);
-        prof_.add_bytes(KP_CG_UPDATE, (6 * s_in - solves) * vec);
-        prof_.add_bytes(KP_CG_DIR, 3 * (s_in - solves) * vec);
         double fb = 0;
         for (const auto &f : flushes_) {
             const int n0 = f[0], n1 = f[1], nsw = f[2];
@@ -1574,20 +1569,29 @@ template <typename T> class TileSolver {
         buf[K % 2] = ytarget;
         buf[(K + 1) % 2] = t_.w.get();
         double rho_prev = 1.0 / sigma;
-        auto step = [&](int kk, const int *skip, double bytes) {
+        auto step = [&](int kk, const int *skip) {
             const double rho = 1.0 / (2.0 * sigma - rho_prev);
             const double c1 = rho * rho_prev, c2 = 2.0 * rho / cheb_delta_;
-            prof_.begin(st_, KP_CHEB, bytes);
             launch_cheb_step<T>(st_, pr_, td, kk == 1 ? 0 : kk == 2 ? 1 : 2, Sv, buf[kk % 2], t_.r.get(),
                                 buf[(kk + 1) % 2], skip, 1.0 / cheb_theta_, c1, c2, t_.part_d.get());
-            prof_.end(st_);
             rho_prev = rho;
         };
+        // the K - 1 steps run back to back: one event pair times them all
         const double vec = static_cast<double>(last_active_) * td.N * sizeof(cpx<T>);
-        for (int k = 1; k < K; ++k) step(k, t_.c_done.get(), vec * (k == 1 ? 2 : k == 2 ? 3 : 4));
+        double bytes = 0.0;
+        prof_.begin_group(st_, KP_CHEB);
+        for (int k = 1; k < K; ++k) {
+            step(k, t_.c_done.get());
+            bytes += vec * (k == 1 ? 2 : k == 2 ? 3 : 4);
+        }
+        prof_.end_group(st_, K - 1, bytes);
         k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_ / cheb_rho_, 0, cs);
-        step(K, t_.c_inner_done.get(), 0.0);
-        step(K + 1, t_.c_inner_done.get(), 0.0);
+        // extra steps for the columns that failed the check (bytes counted
+        // from the check's outcome are not known here: counted as zero)
+        prof_.begin_group(st_, KP_CHEB);
+        step(K, t_.c_inner_done.get());
+        step(K + 1, t_.c_inner_done.get());
+        prof_.end_group(st_, 2, 0.0);
         k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_, 1, cs);
         GSC_HIP(hipGetLastError());
         inner_total_ += K - 1;
@@ -1599,20 +1603,22 @@ template <typename T> class TileSolver {
         int done_steps = 0;
         int chunk = inner_guess_;
         const T *Sv = sval();
+        // algorithmic bytes per CG step over the columns still active
+        const double vec = static_cast<double>(last_active_ > 0 ? last_active_ : td.R) * td.N * sizeof(cpx<T>);
         while (true) {
             for (int j = 0; j < chunk; ++j) {
-                prof_.begin(st_, KP_SPMM_S, mat_bytes());
+                prof_.begin(st_, KP_SPMM_S, mat_bytes() + 2 * vec);
                 launch_spmm_S<T>(st_, pr_, td, Sv, t_.d.get(), t_.w.get(), t_.c_inner_done.get(), t_.part_d.get(),
                                  ctr(KP_SPMM_S));
                 prof_.end(st_);
                 k_cg_a<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), cs);
-                prof_.begin(st_, KP_CG_UPDATE, 0.0);
+                prof_.begin(st_, KP_CG_UPDATE, 6 * vec);
                 k_cg_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_inner_done.get(), t_.c_cg_first.get(),
                                                   t_.c_cg_a.get(), t_.d.get(), t_.w.get(), y, t_.res.get(),
                                                   t_.part_d.get(), ctr(KP_CG_UPDATE));
                 prof_.end(st_);
                 k_cg_b<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), o.inner_max_iter, cs);
-                prof_.begin(st_, KP_CG_DIR, 0.0);
+                prof_.begin(st_, KP_CG_DIR, 3 * vec);
                 k_cg_dir<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_inner_done.get(), t_.c_cg_b.get(),
                                                t_.res.get(), t_.d.get(), ctr(KP_CG_DIR));
                 prof_.end(st_);
