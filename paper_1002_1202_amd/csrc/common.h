@@ -139,6 +139,11 @@ struct Clusters {
     int C = 0;
     int nc = 0;
     DevBuf<int32_t> ptr, col, blk;
+    // packed walk for the Chebyshev step: pack[u] = col[u] | (row mask << 24),
+    // the mask's bit i set when row c*C + i stores a block in column col[u];
+    // perm lists the stored blocks in walk order (u, then i) and sptr[c] is
+    // cluster c's first position in perm (empty when nb >= 2^24)
+    DevBuf<int32_t> pack, perm, sptr;
 };
 
 struct Pair {

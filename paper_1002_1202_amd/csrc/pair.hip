@@ -50,6 +50,31 @@ void build_clusters(Pair &p, int C) {
     GSC_HIP(hipMemcpyAsync(p.cl.ptr.get(), ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, st));
     GSC_HIP(hipMemcpyAsync(p.cl.col.get(), col.data(), col.size() * 4, hipMemcpyHostToDevice, st));
     GSC_HIP(hipMemcpyAsync(p.cl.blk.get(), blk.data(), blk.size() * 4, hipMemcpyHostToDevice, st));
+    if (nb < (int64_t{1} << 24) && C <= 8) {
+        std::vector<int32_t> pack(col.size()), perm, sptr(nc + 1, 0);
+        perm.reserve(p.nnzb);
+        for (int c = 0; c < nc; ++c) {
+            sptr[c] = static_cast<int32_t>(perm.size());
+            for (int32_t u = ptr[c]; u < ptr[c + 1]; ++u) {
+                uint32_t mask = 0;
+                for (int i = 0; i < C; ++i) {
+                    const int32_t b = blk[static_cast<size_t>(u) * C + i];
+                    if (b >= 0) {
+                        mask |= 1u << i;
+                        perm.push_back(b);
+                    }
+                }
+                pack[u] = static_cast<int32_t>(static_cast<uint32_t>(col[u]) | (mask << 24));
+            }
+        }
+        sptr[nc] = static_cast<int32_t>(perm.size());
+        p.cl.pack.alloc(pack.size());
+        p.cl.perm.alloc(perm.size());
+        p.cl.sptr.alloc(sptr.size());
+        GSC_HIP(hipMemcpyAsync(p.cl.pack.get(), pack.data(), pack.size() * 4, hipMemcpyHostToDevice, st));
+        GSC_HIP(hipMemcpyAsync(p.cl.perm.get(), perm.data(), perm.size() * 4, hipMemcpyHostToDevice, st));
+        GSC_HIP(hipMemcpyAsync(p.cl.sptr.get(), sptr.data(), sptr.size() * 4, hipMemcpyHostToDevice, st));
+    }
     GSC_HIP(hipStreamSynchronize(st));
 }
 

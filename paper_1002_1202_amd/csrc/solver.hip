@@ -1034,6 +1034,7 @@ int pick_groups(int64_t rows, int colchunks, int target_blocks) {
 template <typename T> struct Tile {
     TileDims td{};
     DevBuf<cpx<T>> p, q, r, res, d, w, ring, ringT;
+    DevBuf<T> scl;            // S blocks in cluster walk order (cluster Chebyshev step)
     DevBuf<cpx<T>> Xown, P;
     cpx<T> *X = nullptr;
     size_t ldk = 0;
@@ -1199,6 +1200,11 @@ template <typename T> class TileSolver {
         const dim3 eg(td.Rp / 64, td.G), eb(kBlock);
         const int cb = div_up(td.Rp, 256);
         const size_t NR = static_cast<size_t>(td.N) * td.Rp;
+        if (td.variant == 1) {
+            const size_t nv = static_cast<size_t>(pr_.nnzb) * pr_.B * pr_.B;
+            if (t_.scl.n != nv) t_.scl.alloc(nv);
+            launch_permute_blocks<T>(st_, pr_, sval(), t_.scl.get());
+        }
         k_init_cols<<<cb, 256, 0, st_>>>(td.R, td.Rp, seed0, cs);
         k_init_shifts<<<div_up(static_cast<int64_t>(td.K) * td.Rp, 256), 256, 0, st_>>>(td.K, td.R, td.Rp, ss);
         if (full_) {
@@ -1572,8 +1578,13 @@ template <typename T> class TileSolver {
         auto step = [&](int kk, const int *skip) {
             const double rho = 1.0 / (2.0 * sigma - rho_prev);
             const double c1 = rho * rho_prev, c2 = 2.0 * rho / cheb_delta_;
-            launch_cheb_step<T>(st_, pr_, td, kk == 1 ? 0 : kk == 2 ? 1 : 2, Sv, buf[kk % 2], t_.r.get(),
-                                buf[(kk + 1) % 2], skip, 1.0 / cheb_theta_, c1, c2, t_.part_d.get());
+            const int mode = kk == 1 ? 0 : kk == 2 ? 1 : 2;
+            if (td.variant == 1)
+                launch_cheb_cl<T>(st_, pr_, td, mode, t_.scl.get(), buf[kk % 2], t_.r.get(), buf[(kk + 1) % 2], skip,
+                                  1.0 / cheb_theta_, c1, c2, t_.part_d.get());
+            else
+                launch_cheb_step<T>(st_, pr_, td, mode, Sv, buf[kk % 2], t_.r.get(), buf[(kk + 1) % 2], skip,
+                                    1.0 / cheb_theta_, c1, c2, t_.part_d.get());
             rho_prev = rho;
         };
         // the K - 1 steps run back to back: one event pair times them all

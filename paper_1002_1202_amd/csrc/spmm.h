@@ -27,6 +27,15 @@ void launch_cheb_split(hipStream_t st, const Pair &pr, const TileDims &td, int m
                        const cpx<T> *r, cpx<T> *yio, const int *skip, double inv_theta, double c1, double c2,
                        double *partial);
 
+// cluster walk of the Chebyshev step (variant 1): the S blocks in walk order
+// (launch_permute_blocks, once per solve) and the fused step over them
+template <typename T>
+void launch_permute_blocks(hipStream_t st, const Pair &pr, const T *src, T *dst);
+template <typename T>
+void launch_cheb_cl(hipStream_t st, const Pair &pr, const TileDims &td, int mode, const T *Scl, const cpx<T> *y,
+                    const cpx<T> *r, cpx<T> *yio, const int *skip, double inv_theta, double c1, double c2,
+                    double *partial);
+
 int slab_groups(int nb);
 template <typename T>
 void launch_spmm_seed_slab(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const T *Hv,

@@ -334,31 +334,32 @@ def test_slab_kernel_water_and_si(ctx, si216, carry):
             assert rel(res.G_proj[:, :, 0], X[:, np.arange(len(rhs)), rhs]) < 1e-10
 
 
-@pytest.mark.parametrize("hint", [1, 2])
-def test_split_chebyshev_kernel(ctx, si216, hint):
-    """The Chebyshev step on 32-column stripes with the block's orbitals split
-    over the two half-waves (both cache policies for the streamed vectors),
+@pytest.mark.parametrize("kernel,hint", [(4, 1), (4, 2), (2, 1)])
+def test_chebyshev_kernel_variants(ctx, si216, kernel, hint):
+    """The Chebyshev step of the other product layouts: 32-column stripes
+    with the block's orbitals split over the two half-waves (kernel 4, both
+    cache policies for the streamed vectors) and the cluster walk (kernel 2),
     B = 4 and B = 6, a ragged column tail (70 rhs -> 2 tiles of 64), FP64
     and complex64 products."""
     from paper_1002_1202_amd import api
-    print(f"case: split chebyshev stream_hint={hint}", flush=True)
+    print(f"case: chebyshev spmm_kernel={kernel} stream_hint={hint}", flush=True)
     for c in (si216[0], configs.water_small(n_mol=40, n_rhs=23)):
         s = c["system"]
         S, H, _ = oased.dense_pair(s)
         pair, _ = api.pair_from_system(ctx, s)
         rhs = c["rhs"][:70]
         X = ogreen.solve_dense(H, S, c["z"], rhs)
-        res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, spmm_kernel=4, inner_method=2,
+        res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, spmm_kernel=kernel, inner_method=2,
                         stream_hint=hint, recheck=True)
         print(f"  {s.name}: iters={res.outer_iters} inner={res.inner_iters} err={rel(res.G_cols, X):.2e}",
               flush=True)
         assert rel(res.G_cols, X) < 1e-10
         assert res.res_true.max() < 1e-10
         proj = rhs[:, None]
-        res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, spmm_kernel=4, inner_method=2,
+        res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, spmm_kernel=kernel, inner_method=2,
                         stream_hint=hint, carry="projected", proj=proj)
         assert rel(res.G_proj[:, :, 0], X[:, np.arange(len(rhs)), rhs]) < 1e-10
-        resm = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-6, spmm_kernel=4, inner_method=2,
+        resm = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-6, spmm_kernel=kernel, inner_method=2,
                          stream_hint=hint, precision="mixed")
         print(f"  mixed err={rel(resm.G_cols, X):.2e}", flush=True)
         assert rel(resm.G_cols, X) < 1e-3
