@@ -13,5 +13,7 @@ Modules:
   spectral      closed forms from the generalised eigen-decomposition (pins)
   shifted_cocg  the method's recurrences step by step (seed, pi, switching,
                 projected carry with collinear restart, z-derivative carry)
+  lanczos       the generalised Lanczos process (Sec. 3.2) and the continued
+                fraction of G_jj(z)
 """
-from . import ased, green, spectral, shifted_cocg  # noqa: F401
+from . import ased, green, spectral, shifted_cocg, lanczos  # noqa: F401
