@@ -219,6 +219,31 @@ gsc_status gsc_solve(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const doubl
                      const int64_t *proj_idx, double *G_proj, int out_mem,
                      gsc_stats *stats);
 
+/* ---- generalised Lanczos + continued fraction (Sec. 3.2) ----------------- */
+/* Diagonal Green's-function elements G_jj(z_k), j = rhs_idx[r], by the
+ * S-orthonormal three-term recursion of M = S^{-1} H (eqs. 1.13, 1.18)
+ * started at S^{-1} e_j, and the continued fraction
+ *   G_jj(z) = (S^{-1})_jj / (z - a_0 - b_1^2 / (z - a_1 - b_2^2 / ...)).
+ * Each step costs one product with H and one inner solve with S (as in
+ * gsc_solve: first solve by CG, then opts->inner_method); no per-shift
+ * vectors are kept.  A right-hand side stops when, at a check every
+ * check_every steps, its fraction changed by at most tol x max_k |G_jj(z_k)|
+ * since the previous check, or when its Krylov space is exhausted; at most
+ * m_max steps (check_every = 0: exactly m_max steps).
+ * Arguments: rhs_idx HOST [nrhs], 0 <= rhs_idx[r] < N; z HOST [nshift]
+ * complex with Im z_k > 0.  Outputs: G_diag [nshift][nrhs] complex (per
+ * out_mem); coef_a, coef_b HOST [nrhs][m_max] (may be NULL): a_n and b_n of
+ * each right-hand side (b_0 = 0; entries past its step count are 0); steps
+ * HOST [nrhs] (may be NULL).  Uses opts->precision, inner_tol,
+ * inner_max_iter, inner_method, rhs_tile (right-hand sides per tile).
+ * Returns GSC_NOT_CONVERGED when some right-hand side used all m_max steps
+ * with checks enabled (outputs are still written), GSC_E_ARG for invalid
+ * arguments. */
+gsc_status gsc_lanczos_green(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const double *z, int nrhs,
+                             const int64_t *rhs_idx, int m_max, double tol, int check_every,
+                             const gsc_opts *opts, double *G_diag, double *coef_a, double *coef_b,
+                             int *steps, int out_mem, gsc_stats *stats);
+
 /* Mulliken charge and band energy per orbital a = orb_idx[r] (Sec. 2.2),
  * spin 2, quadrature weights w[k] (HOST) over E_k = Re z_k:
  *   q_a = -(2/pi) sum_k w_k Im[(S G_k)_aa],

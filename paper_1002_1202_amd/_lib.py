@@ -72,6 +72,9 @@ SIGNATURES = {
     "gsc_band_energy_vjp": (C.c_int, [_VP, _VP, C.c_int, _DP, _DP, C.c_double, C.POINTER(Opts),
                                       _VP, _VP, _DP, C.c_int, C.POINTER(Stats)]),
     "gsc_solve_batched": (C.c_int, [_VP, C.c_int, C.POINTER(Problem), C.POINTER(Opts)]),
+    "gsc_lanczos_green": (C.c_int, [_VP, _VP, C.c_int, _DP, C.c_int, _I64P, C.c_int, C.c_double, C.c_int,
+                                    C.POINTER(Opts), _VP, _DP, _DP, C.POINTER(C.c_int), C.c_int,
+                                    C.POINTER(Stats)]),
     "gsc_profile_enable": (C.c_int, [_VP, C.c_int]),
     "gsc_profile_select": (C.c_int, [_VP, C.c_char_p]),
     "gsc_profile_read": (C.c_int, [_VP, C.c_char_p, _DP, C.POINTER(C.c_longlong), _DP]),

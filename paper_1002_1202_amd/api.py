@@ -318,6 +318,48 @@ def mulliken_band(ctx: Context, pair: Pair, z, w, orb, **opt):
     return q, e, eb.value, info
 
 
+@dataclass
+class LanczosResult:
+    G_diag: object          # [K][R] complex128 (numpy or torch device tensor)
+    a: np.ndarray           # [R][m_max] Lanczos coefficients a_n
+    b: np.ndarray           # [R][m_max] b_n (b_0 = 0)
+    steps: np.ndarray       # [R] steps taken per right-hand side
+    status: int
+    outer_iters: int
+    inner_iters: int
+    shift_rhs_iters: int
+    seconds: float
+
+
+def lanczos_green(ctx: Context, pair: Pair, z, rhs, m_max: int = 2000, tol: float = 1e-10, check_every: int = 16,
+                  out: str = "host", **opt) -> LanczosResult:
+    """Diagonal Green's-function elements G_jj(z_k), j in rhs, by the
+    generalised Lanczos process and its continued fraction (Sec. 3.2).
+    ``out``: "host" (numpy) or "device" (torch) for G_diag."""
+    z = np.ascontiguousarray(z, dtype=np.complex128)
+    rhs = np.ascontiguousarray(rhs, dtype=np.int64)
+    K, R = z.shape[0], rhs.shape[0]
+    opts = make_opts(**opt)
+    if out == "device":
+        import torch
+        G = torch.empty((K, R), dtype=torch.complex128, device=f"cuda:{ctx.device}")
+        mem = L.MEM_DEVICE
+    else:
+        G = np.empty((K, R), dtype=np.complex128)
+        mem = L.MEM_HOST
+    a = np.zeros((R, m_max))
+    b = np.zeros((R, m_max))
+    steps = np.zeros(R, dtype=np.int32)
+    st = L.Stats()
+    status = ctx.lib.gsc_lanczos_green(ctx.h, pair.h, K, _ptr(_complex_view(z)), R, _ptr(rhs, C.c_int64), m_max,
+                                       float(tol), check_every, C.byref(opts),
+                                       C.cast(C.c_void_p(G.data_ptr()), C.c_void_p) if mem == L.MEM_DEVICE
+                                       else _vp(G.view(np.float64)), _ptr(a), _ptr(b), _ptr(steps, C.c_int), mem,
+                                       C.byref(st))
+    L.check(status)
+    return LanczosResult(G, a, b, steps, status, st.outer_iters, st.inner_iters, st.shift_rhs_iters, st.seconds)
+
+
 def band_energy_vjp(ctx: Context, pair: Pair, z, w, grad_E: float = 1.0, dH=None, dS=None, **opt):
     """Band energy over all orbitals and its gradients on the stored entries:
     dH += grad_E dE/dH_bc, dS += grad_E dE/dS_bc (zeros when not given).

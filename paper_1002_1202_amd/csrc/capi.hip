@@ -373,6 +373,45 @@ gsc_status gsc_solve(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const doubl
     });
 }
 
+gsc_status gsc_lanczos_green(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const double *z, int nrhs,
+                             const int64_t *rhs_idx, int m_max, double tol, int check_every,
+                             const gsc_opts *opts, double *G_diag, double *coef_a, double *coef_b,
+                             int *steps, int out_mem, gsc_stats *stats) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr && pair != nullptr, "ctx/pair must not be NULL");
+        gsc_opts o;
+        gsc_opts_default(&o);
+        if (opts) o = *opts;
+        validate_opts(o);
+        validate_shifts(nshift, z, -1);
+        const Pair &p = pair->p;
+        GSC_REQUIRE(nrhs >= 1 && rhs_idx != nullptr, "need at least one right-hand side index");
+        for (int r = 0; r < nrhs; ++r) GSC_REQUIRE(rhs_idx[r] >= 0 && rhs_idx[r] < p.n, "rhs index out of range");
+        GSC_REQUIRE(m_max >= 1, "m_max must be >= 1");
+        GSC_REQUIRE(check_every >= 0, "check_every must be >= 0");
+        GSC_REQUIRE(check_every == 0 || tol > 0.0, "tol must be positive when checks are enabled");
+        GSC_REQUIRE(G_diag != nullptr, "G_diag must not be NULL");
+        DeviceGuard g(ctx->c.device);
+        LanczosRequest req;
+        req.pair = &p;
+        req.K = nshift;
+        req.z = z;
+        req.P = nrhs;
+        req.rhs_idx = rhs_idx;
+        req.m_max = m_max;
+        req.tol = tol;
+        req.check_every = check_every;
+        req.opts = o;
+        req.G_diag = G_diag;
+        req.coef_a = coef_a;
+        req.coef_b = coef_b;
+        req.steps = steps;
+        req.out_mem = out_mem;
+        req.stats = stats;
+        return run_lanczos(ctx->c, req);
+    });
+}
+
 gsc_status gsc_mulliken_band(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const double *z, const double *w,
                              int norb, const int64_t *orb_idx, const gsc_opts *opts, double *q_orb,
                              double *e_orb, double *e_band, int out_mem, gsc_stats *stats) {

@@ -47,6 +47,26 @@ struct SolveRequest {
 };
 
 gsc_status run_solve(Ctx &ctx, SolveRequest &req);
+
+// Generalised Lanczos + continued fraction for G_jj (unit right-hand sides).
+struct LanczosRequest {
+    const Pair *pair = nullptr;
+    int K = 0;
+    const double *z = nullptr;          // host, 2K
+    int P = 0;                          // number of right-hand sides e_j
+    const int64_t *rhs_idx = nullptr;   // host [P]
+    int m_max = 0;
+    double tol = 0.0;
+    int check_every = 0;
+    gsc_opts opts{};
+    double *G_diag = nullptr;           // [K][P] complex, per out_mem
+    double *coef_a = nullptr;           // host [P][m_max] or null
+    double *coef_b = nullptr;           // host [P][m_max] or null
+    int *steps = nullptr;               // host [P] or null
+    int out_mem = GSC_MEM_HOST;
+    gsc_stats *stats = nullptr;
+};
+gsc_status run_lanczos(Ctx &ctx, LanczosRequest &req);
 // Many projected-carry solves at once: one job per (system, rhs tile), each
 // iterating as a captured hipGraph of `graph_iters` outer iterations on one
 // of up to `max_streams` streams; iters[s] receives the iterations run.

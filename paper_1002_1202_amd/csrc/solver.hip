@@ -1023,6 +1023,229 @@ __global__ void k_true_residual(int K, int R, int N, int B, const int32_t *rowpt
 // ------------------------------------------------------------------ driver
 namespace {
 
+// ------------------------------------------------------------------ generalised Lanczos
+// Sec. 3.2, eqs. 1.13 and 1.18: the S-orthonormal three-term recursion of
+// M = S^{-1} H started at S^{-1} e_j, and G_jj(z) from its continued
+// fraction.  The Lanczos vectors are real: process p = 2c + q lives in part
+// q (0 real, 1 imaginary) of column c, so the products and the inner
+// S-solve act on two processes at once and only the dots are split.
+
+// sums over the 4 waves of a block, two values per lane -> two partial planes
+__device__ inline void wave_partial_store2(double v0, double v1, double *part, int G, int g, int Rp, int col) {
+    __shared__ double red[2][kWavesPerBlock][64];
+    const int lane = threadIdx.x & 63;
+    red[0][threadIdx.x >> 6][lane] = v0;
+    red[1][threadIdx.x >> 6][lane] = v1;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < kWavesPerBlock; ++k) { s0 += red[0][k][lane]; s1 += red[1][k][lane]; }
+        part[static_cast<size_t>(g) * Rp + col] = s0;
+        part[(static_cast<size_t>(G) + g) * Rp + col] = s1;
+    }
+}
+
+// r = e_j in each process's part (res = d = r for a CG start), partial |r|^2
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lz_unit(int N, int Rp, int Lr, int P, const int64_t *rhs, cpx<T> *r,
+                                                    cpx<T> *res, cpx<T> *d, double *partial) {
+    ELEM_LOOP_BEGIN
+    const int64_t jr = 2 * col < P ? rhs[2 * col] : -1;
+    const int64_t ji = 2 * col + 1 < P ? rhs[2 * col + 1] : -1;
+    double acc = 0.0;
+    for (int i = i0 + wv; i < i1; i += kWavesPerBlock) {
+        const cpx<T> v{i == jr ? T(1) : T(0), i == ji ? T(1) : T(0)};
+        const size_t e = static_cast<size_t>(i) * Rp + col;
+        r[e] = v;
+        res[e] = v;
+        d[e] = v;
+        acc += static_cast<double>(v.re) * v.re + static_cast<double>(v.im) * v.im;
+    }
+    wave_partial_store(acc, partial, g, Rp, col);
+}
+
+// v_j = (S^{-1} e_j)_j = ||S^{-1} e_j||_S^2 of every process, 1/sqrt(v_j), and
+// the process state (a process without a right-hand side is finished)
+template <typename T>
+__global__ void k_lz_vj(int P, int Rp, const int64_t *rhs, const cpx<T> *v, double *vj, double *inv, int *steps,
+                        int *done) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= 2 * Rp) return;
+    double val = 0.0;
+    if (p < P) {
+        const cpx<T> x = v[static_cast<size_t>(rhs[p]) * Rp + (p >> 1)];
+        val = (p & 1) ? x.im : x.re;
+    }
+    const bool ok = p < P && val > 0.0 && isfinite(val);
+    vj[p] = ok ? val : 0.0;
+    inv[p] = ok ? 1.0 / sqrt(val) : 0.0;
+    steps[p] = 0;
+    done[p] = ok ? 0 : 1;
+}
+
+// u^0 = v / sqrt(v_j), u^{-1} = 0 and S u^{-1} = 0 (S u^n is formed by the
+// product of each step)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lz_start(int N, int Rp, int Lr, const double *inv, const cpx<T> *v,
+                                                     cpx<T> *u, cpx<T> *up, cpx<T> *sp) {
+    ELEM_LOOP_BEGIN
+    const T ir = static_cast<T>(inv[2 * col]), ii = static_cast<T>(inv[2 * col + 1]);
+    for (int i = i0 + wv; i < i1; i += kWavesPerBlock) {
+        const size_t e = static_cast<size_t>(i) * Rp + col;
+        const cpx<T> x = v[e];
+        u[e] = {x.re * ir, x.im * ii};
+        up[e] = {0, 0};
+        sp[e] = {0, 0};
+    }
+}
+
+// a_n = u^T H u of both processes of a column from the product's partials
+__global__ __launch_bounds__(kBlock) void k_lz_reduce_a(int Rp, int Gs, const double *part, int n, int mmax,
+                                                        double *a, int *steps, const int *done) {
+    __shared__ double lds[kBlock];
+    const int c = blockIdx.x;
+    double s0 = 0.0, s1 = 0.0;
+    for (int g = threadIdx.x; g < Gs; g += kBlock) {
+        s0 += part[static_cast<size_t>(g) * Rp + c];
+        s1 += part[(static_cast<size_t>(Gs) + g) * Rp + c];
+    }
+    s0 = block_sum(s0, lds);
+    s1 = block_sum(s1, lds);
+    if (threadIdx.x != 0) return;
+    for (int q = 0; q < 2; ++q) {
+        const int p = 2 * c + q;
+        if (done[p]) continue;
+        a[static_cast<size_t>(p) * mmax + n] = q ? s1 : s0;
+        steps[p] = n + 1;
+    }
+}
+
+// w' = w - a_n u - b_n u^{n-1} (over w) and the partial w'^T S w' of both
+// parts, with S w' = h - a_n S u - b_n S u^{n-1} (h = H u = S w up to the
+// inner solve's tolerance; S u and S u^{n-1} are the products' fresh values)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lz_update(int N, int Rp, int Lr, int G, int n, int mmax, const double *a,
+                                                      const double *b, cpx<T> *w, const cpx<T> *u,
+                                                      const cpx<T> *up, const cpx<T> *h, const cpx<T> *s,
+                                                      const cpx<T> *sp, double *part) {
+    ELEM_LOOP_BEGIN
+    const size_t pr = static_cast<size_t>(2 * col) * mmax, pi = pr + mmax;
+    const T ar = static_cast<T>(a[pr + n]), ai = static_cast<T>(a[pi + n]);
+    const T br = n > 0 ? static_cast<T>(b[pr + n]) : T(0), bi = n > 0 ? static_cast<T>(b[pi + n]) : T(0);
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int i = i0 + wv; i < i1; i += kWavesPerBlock) {
+        const size_t e = static_cast<size_t>(i) * Rp + col;
+        const cpx<T> uv = u[e], upv = up[e], sv = s[e], spv = sp[e], wv_ = w[e], hv = h[e];
+        const cpx<T> wn{wv_.re - ar * uv.re - br * upv.re, wv_.im - ai * uv.im - bi * upv.im};
+        const cpx<T> sn{hv.re - ar * sv.re - br * spv.re, hv.im - ai * sv.im - bi * spv.im};
+        w[e] = wn;
+        acc0 += static_cast<double>(wn.re) * sn.re;
+        acc1 += static_cast<double>(wn.im) * sn.im;
+    }
+    wave_partial_store2(acc0, acc1, part, G, g, Rp, col);
+}
+
+// b_{n+1} = ||w'||_S and 1/b_{n+1} per process; a finished process, or one
+// whose Krylov space is exhausted (b_{n+1} ~ 0), gets 1/b = 0 (its vectors
+// become zero and stay zero)
+__global__ __launch_bounds__(kBlock) void k_lz_reduce_b(int Rp, int G, const double *part, int n, int mmax,
+                                                        const double *a, double *b, double *inv, int *done) {
+    __shared__ double lds[kBlock];
+    const int c = blockIdx.x;
+    double s0 = 0.0, s1 = 0.0;
+    for (int g = threadIdx.x; g < G; g += kBlock) {
+        s0 += part[static_cast<size_t>(g) * Rp + c];
+        s1 += part[(static_cast<size_t>(G) + g) * Rp + c];
+    }
+    s0 = block_sum(s0, lds);
+    s1 = block_sum(s1, lds);
+    if (threadIdx.x != 0) return;
+    for (int q = 0; q < 2; ++q) {
+        const int p = 2 * c + q;
+        if (done[p]) { inv[p] = 0.0; continue; }
+        const double bn = sqrt(fmax(q ? s1 : s0, 0.0));
+        const double an = a[static_cast<size_t>(p) * mmax + n];
+        if (!(bn > 1e-14 * fmax(1.0, fabs(an))) || !isfinite(bn)) {
+            done[p] = 1;
+            inv[p] = 0.0;
+            continue;
+        }
+        if (n + 1 < mmax) b[static_cast<size_t>(p) * mmax + n + 1] = bn;
+        inv[p] = 1.0 / bn;
+    }
+}
+
+// u^{n+1} = w' / b_{n+1}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lz_scale(int N, int Rp, int Lr, const double *inv, const cpx<T> *w,
+                                                     cpx<T> *un) {
+    ELEM_LOOP_BEGIN
+    const T ir = static_cast<T>(inv[2 * col]), ii = static_cast<T>(inv[2 * col + 1]);
+    for (int i = i0 + wv; i < i1; i += kWavesPerBlock) {
+        const size_t e = static_cast<size_t>(i) * Rp + col;
+        const cpx<T> x = w[e];
+        un[e] = {x.re * ir, x.im * ii};
+    }
+}
+
+// G_jj(z_k) = v_j / (z_k - a_0 - b_1^2 / (z_k - a_1 - ...)) at each process's
+// current depth, evaluated from the bottom.  Check mode: compare with the
+// previous check (finished when the change over all shifts is at most tol
+// times the largest |G|); final mode: write G.
+__global__ __launch_bounds__(kBlock) void k_lz_cf(int K, int mmax, const c128 *z, const double *a, const double *b,
+                                                  const double *vj, const int *steps, c128 *gprev, double tol,
+                                                  int *done, int final_, c128 *out, int ldo, int p0) {
+    __shared__ double l1[kBlock], l2[kBlock];
+    const int p = blockIdx.x;
+    const int d = steps[p];
+    const double *ap = a + static_cast<size_t>(p) * mmax, *bp = b + static_cast<size_t>(p) * mmax;
+    double dmax = 0.0, gmax = 0.0;
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+        c128 g{0.0, 0.0};
+        if (d > 0 && vj[p] > 0.0) {
+            const c128 zk = z[k];
+            c128 t{zk.re - ap[d - 1], zk.im};
+            for (int i = d - 2; i >= 0; --i) {
+                const c128 q = cdiv(c128{bp[i + 1] * bp[i + 1], 0.0}, t);
+                t = c128{zk.re - ap[i] - q.re, zk.im - q.im};
+            }
+            g = cdiv(c128{vj[p], 0.0}, t);
+        }
+        if (final_) {
+            out[static_cast<size_t>(k) * ldo + p0 + p] = g;
+        } else {
+            const size_t o = static_cast<size_t>(p) * K + k;
+            dmax = fmax(dmax, cabs(g - gprev[o]));
+            gmax = fmax(gmax, cabs(g));
+            gprev[o] = g;
+        }
+    }
+    if (final_) return;
+    l1[threadIdx.x] = dmax;
+    l2[threadIdx.x] = gmax;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            l1[threadIdx.x] = fmax(l1[threadIdx.x], l1[threadIdx.x + s]);
+            l2[threadIdx.x] = fmax(l2[threadIdx.x], l2[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && !done[p] && l1[0] <= tol * l2[0]) done[p] = 1;
+}
+
+__global__ void k_lz_fill(size_t n, c128 v, c128 *x) {
+    const size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < n) x[t] = v;
+}
+
+// a column is finished when both of its processes are
+__global__ void k_lz_cols(int Rp, const int *done, int *cdone) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < Rp) cdone[c] = (done[2 * c] && done[2 * c + 1]) ? 1 : 0;
+}
+
 int pick_groups(int64_t rows, int colchunks, int target_blocks) {
     int g = std::max(1, target_blocks / std::max(1, colchunks));
     g = static_cast<int>(std::min<int64_t>(g, (rows + 3) / 4));
@@ -1348,6 +1571,81 @@ template <typename T> class TileSolver {
         GSC_HIP(hipGetLastError());
         if (prof_.on) account_bytes(n);
         return n;
+    }
+
+
+    // Generalised Lanczos (Sec. 3.2) for the P processes of this tile (two per
+    // column).  Device outputs: a, b [2Rp][mmax] (zeroed here; b[p][0] = 0),
+    // steps, vj [2Rp], G [K][ldo] at column offset p0.  Returns the steps run.
+    int run_lanczos(const gsc_opts &o, double inner_tol, const int64_t *rhs, int P, int mmax, double tol, int check,
+                    double *a, double *b, int *steps, double *vj, c128 *gout, int ldo, int p0) {
+        auto &td = t_.td;
+        ColState cs = t_.cols();
+        const dim3 eg(td.Rp / 64, td.G), eb(kBlock);
+        const int cb = div_up(td.Rp, 256);
+        const size_t NR = static_cast<size_t>(td.N) * td.Rp;
+        const int Gm = std::max(td.G, td.Gs);
+        DevBuf<double> part(3 * static_cast<size_t>(Gm) * td.Rp), inv(2 * static_cast<size_t>(td.Rp));
+        DevBuf<int> done(2 * static_cast<size_t>(td.Rp));
+        DevBuf<c128> gprev(static_cast<size_t>(std::max(P, 1)) * td.K);
+        DevBuf<cpx<T>> ub0(NR), ub1(NR), sb0(NR), sb1(NR);
+        GSC_HIP(hipMemsetAsync(a, 0, 2 * static_cast<size_t>(td.Rp) * mmax * sizeof(double), st_));
+        GSC_HIP(hipMemsetAsync(b, 0, 2 * static_cast<size_t>(td.Rp) * mmax * sizeof(double), st_));
+        k_init_cols<<<cb, 256, 0, st_>>>(td.R, td.Rp, 0, cs);
+        k_lz_unit<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, P, rhs, t_.r.get(), t_.res.get(), t_.d.get(),
+                                         part.get());
+        k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, part.get(), 1, inner_tol, cs);
+        inner_tol_ = inner_tol;
+        cpx<T> *v = t_.ring.get();   // S^{-1} e_j, then the inner solve's output w
+        inner_solve_cg(o, cs, v);
+        if (o.inner_method != 1) setup_chebyshev(o, inner_tol);
+        cpx<T> *u = ub0.get(), *up = ub1.get(), *s = sb0.get(), *sp = sb1.get();
+        k_lz_vj<T><<<div_up(2 * td.Rp, 256), 256, 0, st_>>>(P, td.Rp, rhs, v, vj, inv.get(), steps, done.get());
+        k_lz_start<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, inv.get(), v, u, up, sp);
+        k_lz_fill<<<div_up(gprev.n, 256), 256, 0, st_>>>(gprev.n, c128{1e300, 0.0}, gprev.get());
+        k_lz_cols<<<cb, 256, 0, st_>>>(td.Rp, done.get(), cs.done);
+        GSC_HIP(hipGetLastError());
+        check_status(false);
+        const T *Hv = hval(), *Sv = sval();
+        const size_t Gs = static_cast<size_t>(td.Gs);
+        int ran = 0;
+        for (int n = 0; n < mmax; ++n) {
+            prof_.begin(st_, KP_SPMM_SEED, 2.0 * mat_bytes() + 3.0 * last_active_ * td.N * sizeof(cpx<T>));
+            launch_lz_hprod<T>(st_, pr_, td, Hv, Sv, u, t_.r.get(), s, cs.done, part.get());
+            prof_.end(st_);
+            k_lz_reduce_a<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, part.get(), n, mmax, a, steps, done.get());
+            ran = n + 1;
+            if (n == mmax - 1) break;
+            k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, part.get() + 2 * Gs * td.Rp, 0, inner_tol, cs);
+            if (!cheb_ok_) {
+                k_copy_vec<T><<<div_up(NR, 256), 256, 0, st_>>>(NR, t_.r.get(), t_.res.get());
+                k_copy_vec<T><<<div_up(NR, 256), 256, 0, st_>>>(NR, t_.r.get(), t_.d.get());
+            }
+            inner_solve(o, cs, v);
+            prof_.begin(st_, KP_UPDATE_R, 7.0 * last_active_ * td.N * sizeof(cpx<T>));
+            k_lz_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, td.G, n, mmax, a, b, v, u, up, t_.r.get(), s, sp,
+                                               part.get());
+            prof_.end(st_);
+            k_lz_reduce_b<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, part.get(), n, mmax, a, b, inv.get(), done.get());
+            prof_.begin(st_, KP_P_UPDATE, 2.0 * last_active_ * td.N * sizeof(cpx<T>));
+            k_lz_scale<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, inv.get(), v, up);
+            prof_.end(st_);
+            std::swap(u, up);
+            std::swap(s, sp);
+            GSC_HIP(hipGetLastError());
+            if (check > 0 && (n + 1) % check == 0) {
+                k_lz_cf<<<P, kBlock, 0, st_>>>(td.K, mmax, dz_, a, b, vj, steps, gprev.get(), tol, done.get(), 0,
+                                               nullptr, 0, 0);
+                k_lz_cols<<<cb, 256, 0, st_>>>(td.Rp, done.get(), cs.done);
+                const Status st = check_status(false);
+                if (st.active_cols == 0) break;
+            }
+        }
+        k_lz_cf<<<P, kBlock, 0, st_>>>(td.K, mmax, dz_, a, b, vj, steps, gprev.get(), tol, done.get(), 1, gout, ldo,
+                                       p0);
+        GSC_HIP(hipGetLastError());
+        lz_steps_ = ran;
+        return ran;
     }
 
     int flags() const { return flags_; }
@@ -1700,6 +1998,7 @@ template <typename T> class TileSolver {
     HostStatus hs_;
     int inner_guess_ = 8;
     int last_active_ = 0;
+    int lz_steps_ = 0;
     double inner_tol_ = 1e-12;
     bool cheb_ok_ = false;
     double cheb_theta_ = 1.0, cheb_delta_ = 0.5, cheb_rho_ = 0.5, cheb_lo_ = 0.0, cheb_hi_ = 0.0;
@@ -1987,6 +2286,106 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
     return result;
 }
 
+// Generalised Lanczos for the unit right-hand sides of one request, in tiles
+// of processes (two per column).
+template <typename T>
+gsc_status lanczos_typed(Ctx &ctx, LanczosRequest &req) {
+    const Pair &pr = *req.pair;
+    const gsc_opts &o = req.opts;
+    hipStream_t st = ctx.stream;
+    const int N = static_cast<int>(pr.n);
+    std::vector<double> zh(req.z, req.z + 2 * req.K);
+    DevBuf<c128> dz(req.K);
+    GSC_HIP(hipMemcpyAsync(dz.get(), zh.data(), zh.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    const double inner_tol = default_inner_tol<T>(o);
+    int Pt = o.rhs_tile > 0 ? o.rhs_tile : req.P;
+    if (o.rhs_tile <= 0) {
+        size_t freeb = 0, totalb = 0;
+        GSC_HIP(hipMemGetInfo(&freeb, &totalb));
+        // per column: ~12 vectors plus coefficient rows of two processes
+        const double per_col = 12.0 * N * sizeof(cpx<T>) + 4.0 * req.m_max * sizeof(double) + 32.0 * req.K;
+        const int fit = static_cast<int>(0.6 * static_cast<double>(freeb) / per_col);
+        Pt = std::max(128, std::min(Pt, 2 * fit));
+    }
+    Pt = std::max(2, std::min(Pt, req.P));
+    Pt += Pt & 1;
+    // device output [K][P]
+    DevBuf<c128> gown;
+    c128 *gout = nullptr;
+    if (req.out_mem == GSC_MEM_DEVICE) {
+        gout = reinterpret_cast<c128 *>(req.G_diag);
+    } else {
+        gown.alloc(static_cast<size_t>(req.K) * req.P);
+        gout = gown.get();
+    }
+    hipEvent_t e0, e1;
+    GSC_HIP(hipEventCreate(&e0));
+    GSC_HIP(hipEventCreate(&e1));
+    GSC_HIP(hipEventRecord(e0, st));
+    int max_steps = 0;
+    long long inner = 0, sri = 0;
+    for (int p0 = 0; p0 < req.P; p0 += Pt) {
+        const int P = std::min(Pt, req.P - p0);
+        const int ncol = (P + 1) / 2;
+        const int Rp = (ncol + 63) / 64 * 64;
+        std::vector<int64_t> hr(2 * static_cast<size_t>(Rp), -1);
+        for (int p = 0; p < P; ++p) hr[p] = req.rhs_idx[p0 + p];
+        DevBuf<int64_t> drhs(hr.size());
+        GSC_HIP(hipMemcpyAsync(drhs.get(), hr.data(), hr.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        SolveRequest sreq;
+        sreq.pair = req.pair;
+        sreq.K = req.K;
+        sreq.z = req.z;
+        sreq.R = ncol;
+        sreq.opts = o;
+        sreq.opts.carry = GSC_CARRY_PROJECTED;
+        sreq.out_mem = req.out_mem;
+        TileSolver<T> ts(ctx, sreq, dz.get(), nullptr, nullptr, 0, ncol, Rp, 1, false);
+        ts.allocate();
+        const size_t PR = 2 * static_cast<size_t>(Rp);
+        DevBuf<double> a(PR * req.m_max), b(PR * req.m_max), vj(PR);
+        DevBuf<int> steps(PR);
+        ts.run_lanczos(o, inner_tol, drhs.get(), P, req.m_max, req.tol, req.check_every, a.get(), b.get(),
+                       steps.get(), vj.get(), gout, req.P, p0);
+        std::vector<int> hs(PR);
+        GSC_HIP(hipMemcpyAsync(hs.data(), steps.get(), PR * sizeof(int), hipMemcpyDeviceToHost, st));
+        if (req.coef_a) {
+            GSC_HIP(hipMemcpyAsync(req.coef_a + static_cast<size_t>(p0) * req.m_max, a.get(),
+                                   static_cast<size_t>(P) * req.m_max * sizeof(double), hipMemcpyDeviceToHost, st));
+        }
+        if (req.coef_b) {
+            GSC_HIP(hipMemcpyAsync(req.coef_b + static_cast<size_t>(p0) * req.m_max, b.get(),
+                                   static_cast<size_t>(P) * req.m_max * sizeof(double), hipMemcpyDeviceToHost, st));
+        }
+        GSC_HIP(hipStreamSynchronize(st));
+        for (int p = 0; p < P; ++p) {
+            if (req.steps) req.steps[p0 + p] = hs[p];
+            max_steps = std::max(max_steps, hs[p]);
+            sri += static_cast<long long>(hs[p]) * req.K;
+        }
+        inner += ts.inner_total();
+    }
+    if (req.out_mem != GSC_MEM_DEVICE) {
+        GSC_HIP(hipMemcpyAsync(req.G_diag, gout, static_cast<size_t>(req.K) * req.P * sizeof(c128),
+                               hipMemcpyDeviceToHost, st));
+    }
+    GSC_HIP(hipEventRecord(e1, st));
+    GSC_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    GSC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (req.stats) {
+        req.stats->outer_iters = max_steps;
+        req.stats->inner_iters = inner;
+        req.stats->switches = 0;
+        req.stats->restarts = 0;
+        req.stats->shift_rhs_iters = sri;
+        req.stats->seconds = ms * 1e-3;
+    }
+    return max_steps >= req.m_max && req.check_every > 0 ? GSC_NOT_CONVERGED : GSC_OK;
+}
+
 }  // namespace
 
 gsc_status run_batched(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_iters, int max_streams,
@@ -2006,6 +2405,14 @@ gsc_status run_solve(Ctx &ctx, SolveRequest &req) {
         return solve_typed<float>(ctx, req);
     }
     return solve_typed<double>(ctx, req);
+}
+
+gsc_status run_lanczos(Ctx &ctx, LanczosRequest &req) {
+    if (req.opts.precision == GSC_MIXED) {
+        ensure_f32(const_cast<Pair &>(*req.pair));
+        return lanczos_typed<float>(ctx, req);
+    }
+    return lanczos_typed<double>(ctx, req);
 }
 
 }  // namespace gsc

@@ -36,6 +36,12 @@ void launch_cheb_cl(hipStream_t st, const Pair &pr, const TileDims &td, int mode
                     const cpx<T> *r, cpx<T> *yio, const int *skip, double inv_theta, double c1, double c2,
                     double *partial);
 
+// h = H u and s = S u with the split dots of two packed real Lanczos
+// processes per column
+template <typename T>
+void launch_lz_hprod(hipStream_t st, const Pair &pr, const TileDims &td, const T *Hv, const T *Sv, const cpx<T> *u,
+                     cpx<T> *h, cpx<T> *su, const int *skip, double *part);
+
 int slab_groups(int nb);
 template <typename T>
 void launch_spmm_seed_slab(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const T *Hv,

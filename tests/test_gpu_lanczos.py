@@ -1,0 +1,130 @@
+"""GPU parity of the generalised Lanczos path (Sec. 3.2): G_jj against the
+plain definition (dense LU), the recursion coefficients against the oracle's
+process, fixed-depth fractions against the oracle's fraction, and G_jj at the
+benchmark size against the shifted COCG solver.  Every case prints its name
+before it runs."""
+import numpy as np
+import pytest
+
+from oracle import ased as oased, green as ogreen, lanczos as olz
+from synth import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1002_1202_amd import api
+    return api.Context(0)
+
+
+@pytest.fixture(scope="module")
+def si216():
+    c = configs.si_small(cells=(3, 3, 3), n_shift=16, eta=0.1, n_rhs=70, seed=21)
+    S, H, _ = oased.dense_pair(c["system"])
+    return c, S, H
+
+
+@pytest.mark.parametrize("nrhs", [24, 23, 70])
+def test_lanczos_green_vs_lu(ctx, si216, nrhs):
+    """Converged G_jj for an even, an odd (one empty packed half) and a
+    two-tile-wide rhs count."""
+    from paper_1002_1202_amd import api
+    c, S, H = si216
+    print(f"case: lanczos si216 nrhs={nrhs}", flush=True)
+    pair, _ = api.pair_from_system(ctx, c["system"])
+    rhs = c["rhs"][:nrhs]
+    res = api.lanczos_green(ctx, pair, c["z"], rhs, m_max=1500, tol=1e-11, check_every=8)
+    X = ogreen.solve_dense(H, S, c["z"], rhs)
+    ref = X[:, np.arange(len(rhs)), rhs]
+    print(f"  steps {res.steps.min()}..{res.steps.max()} err={rel(res.G_diag, ref):.2e}", flush=True)
+    assert res.status == 0
+    assert rel(res.G_diag, ref) < 1e-9
+
+
+def test_lanczos_coefficients_vs_oracle(ctx, si216):
+    """The first recursion coefficients agree with the oracle's process
+    (before rounding differences in the loss of orthogonality matter)."""
+    from paper_1002_1202_amd import api
+    c, S, H = si216
+    print("case: lanczos coefficients si216", flush=True)
+    pair, _ = api.pair_from_system(ctx, c["system"])
+    rhs = c["rhs"][:5]
+    m = 12
+    res = api.lanczos_green(ctx, pair, c["z"], rhs, m_max=m, check_every=0)
+    assert (res.steps == m).all()
+    for r, j in enumerate(rhs):
+        a, b, vj = olz.lanczos(H, S, int(j), m)
+        np.testing.assert_allclose(res.a[r], a, rtol=1e-9, atol=1e-9)
+        np.testing.assert_allclose(res.b[r, 1:], b[1:], rtol=1e-9)
+        assert res.b[r, 0] == 0.0
+        # the fixed-depth fraction is the oracle's fraction of the same depth
+        g = olz.continued_fraction(c["z"], a, b, vj)
+        np.testing.assert_allclose(res.G_diag[:, r], g, rtol=1e-9)
+
+
+def test_lanczos_water_mixed_and_device_output(ctx):
+    """B = 6 blocks; complex64 products with FP64 coefficients; G_diag left
+    in device memory."""
+    from paper_1002_1202_amd import api
+    c = configs.water_small(n_mol=40, n_rhs=23)
+    s = c["system"]
+    print("case: lanczos water40 fp64 + mixed, device output", flush=True)
+    S, H, _ = oased.dense_pair(s)
+    pair, _ = api.pair_from_system(ctx, s)
+    rhs = c["rhs"]
+    X = ogreen.solve_dense(H, S, c["z"], rhs)
+    ref = X[:, np.arange(len(rhs)), rhs]
+    res = api.lanczos_green(ctx, pair, c["z"], rhs, m_max=1500, tol=1e-11, check_every=8, out="device")
+    assert rel(res.G_diag.cpu().numpy(), ref) < 1e-9
+    resm = api.lanczos_green(ctx, pair, c["z"], rhs, m_max=1500, tol=1e-6, check_every=8, precision="mixed")
+    print(f"  mixed err={rel(resm.G_diag, ref):.2e} steps={resm.steps.max()}", flush=True)
+    assert rel(resm.G_diag, ref) < 1e-3
+
+
+def test_lanczos_inner_cg(ctx, si216):
+    from paper_1002_1202_amd import api
+    c, S, H = si216
+    print("case: lanczos with CG inner solves", flush=True)
+    pair, _ = api.pair_from_system(ctx, c["system"])
+    rhs = c["rhs"][:6]
+    res = api.lanczos_green(ctx, pair, c["z"], rhs, m_max=1500, tol=1e-11, check_every=8, inner_method=1)
+    X = ogreen.solve_dense(H, S, c["z"], rhs)
+    assert rel(res.G_diag, X[:, np.arange(len(rhs)), rhs]) < 1e-9
+
+
+def test_lanczos_not_converged_and_errors(ctx, si216):
+    from paper_1002_1202_amd import api, _lib
+    c, S, H = si216
+    print("case: lanczos not converged / argument errors", flush=True)
+    pair, _ = api.pair_from_system(ctx, c["system"])
+    res = api.lanczos_green(ctx, pair, c["z"], c["rhs"][:4], m_max=16, tol=1e-12, check_every=8)
+    assert res.status == _lib.GSC_NOT_CONVERGED
+    with pytest.raises(_lib.GscError):
+        api.lanczos_green(ctx, pair, c["z"], [c["system"].n], m_max=8)
+    with pytest.raises(_lib.GscError):
+        api.lanczos_green(ctx, pair, np.array([1.0 + 0.0j]), [0], m_max=8)
+
+
+def test_lanczos_si4096_vs_cocg(ctx):
+    """Benchmark size: Lanczos G_jj of 64 of the si4096 right-hand sides
+    against the projected shifted COCG solver (itself LU-validated) at the
+    same tolerance."""
+    from paper_1002_1202_amd import api
+    cfg = configs.si4096()
+    s, z, rhs = cfg["system"], cfg["z"], cfg["rhs"][:64]
+    print("case: lanczos si4096 64 rhs vs projected COCG", flush=True)
+    pair, _ = api.pair_from_system(ctx, s)
+    lz = api.lanczos_green(ctx, pair, z, rhs, m_max=3000, tol=1e-10, check_every=16)
+    co = api.solve(ctx, pair, z, rhs=rhs, tol=1e-10, carry="projected", proj=rhs[:, None])
+    g = co.G_proj[:, :, 0]
+    print(f"  lanczos steps {lz.steps.min()}..{lz.steps.max()} ({lz.seconds:.3f} s), cocg iters "
+          f"{co.outer_iters}; rel diff {rel(lz.G_diag, g):.2e}", flush=True)
+    assert rel(lz.G_diag, g) < 1e-8
