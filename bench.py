@@ -82,6 +82,44 @@ def cpu_baseline(cfg, iters):
                       f"steps) in {dt:.1f} s"}
 
 
+def lanczos_compare(ctx, cfg):
+    """G_jj of every right-hand side of the workload at every shift by the
+    generalised Lanczos process + continued fraction (Sec. 3.2) and by the
+    projected shifted COCG solver, same tolerance; best of 2 runs each."""
+    import numpy as np
+    import torch
+
+    from paper_1002_1202_amd import api
+
+    s, z, rhs, tol = cfg["system"], cfg["z"], cfg["rhs"], cfg["tol"]
+    pair, _ = api.pair_from_system(ctx, s)
+    best = {}
+    for name in ("lanczos", "cocg_projected"):
+        t_best, out = float("inf"), None
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "lanczos":
+                out = api.lanczos_green(ctx, pair, z, rhs, m_max=4000, tol=tol, check_every=16, out="device")
+            else:
+                out = api.solve(ctx, pair, z, rhs=rhs, tol=tol, carry="projected", proj=rhs[:, None], out="device")
+            torch.cuda.synchronize()
+            t_best = min(t_best, time.perf_counter() - t0)
+        best[name] = (t_best, out)
+    tl, lz = best["lanczos"]
+    tc, co = best["cocg_projected"]
+    g1 = lz.G_diag.cpu().numpy()
+    g2 = co.G_proj[:, :, 0].cpu().numpy()
+    return {"workload": f"{cfg['name']} G_jj: {len(rhs)} rhs x {len(z)} shifts, tol {tol:g}",
+            "lanczos": {"seconds": tl, "steps_min": int(lz.steps.min()), "steps_max": int(lz.steps.max()),
+                        "inner_iters": int(lz.inner_iters),
+                        "value": lz.shift_rhs_iters / tl, "unit": "shift·RHS·steps/s"},
+            "cocg_projected": {"seconds": tc, "outer_iters": int(co.outer_iters),
+                               "value": co.shift_rhs_iters / tc, "unit": UNIT},
+            "speedup_lanczos_vs_cocg": tc / tl,
+            "rel_diff_G_jj": float(np.abs(g1 - g2).max() / np.abs(g2).max())}
+
+
 def batched_compare(ctx):
     """Mixed-precision batched solve vs the plain FP64 batched solve at tol
     1e-6 on the 32-system workload (G_jj, charges, band-energy terms), with
@@ -153,6 +191,7 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate launch shapes on this problem first and use the fastest")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-lanczos", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a copy-like kernel over 1 GiB first (torch.neg: 1 GiB read, 1 GiB written), "
                          "which calibrates the HBM byte counters of a --pmc run")
@@ -271,6 +310,10 @@ def main():
     line["config"]["autotuned"] = tuned is not None
     del Gc
     torch.cuda.empty_cache()
+    if not args.no_lanczos:
+        line["lanczos"] = lanczos_compare(ctx, cfg)
+        print(f"lanczos: {line['lanczos']['lanczos']['seconds']:.3f} s vs projected COCG "
+              f"{line['lanczos']['cocg_projected']['seconds']:.3f} s", file=sys.stderr, flush=True)
     if not args.no_batched:
         line["batched"] = batched_compare(ctx)
     if not args.no_cpu_baseline:

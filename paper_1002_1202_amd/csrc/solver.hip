@@ -567,8 +567,7 @@ __global__ void k_status(int Rp, ColState cs, Status *st) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_r(int N, int Rp, int Lr, const int *done,
                                                      const c128 *alpha, const cpx<T> *q, cpx<T> *r,
-                                                     cpx<T> *res, cpx<T> *d, double *partial,
-                                                     unsigned long long *ctr) {
+                                                     cpx<T> *res, cpx<T> *d, double *partial, int copy) {
     ELEM_LOOP_BEGIN
     double acc = 0.0;
     if (!done[col]) {
@@ -577,8 +576,11 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int N, int Rp, int Lr, cons
             const size_t e = static_cast<size_t>(i) * Rp + col;
             const cpx<T> v = r[e] - a * q[e];
             r[e] = v;
-            res[e] = v;
-            d[e] = v;
+            if (copy) {
+                // starting residual and direction of a CG inner solve
+                res[e] = v;
+                d[e] = v;
+            }
             acc += static_cast<double>(v.re) * v.re + static_cast<double>(v.im) * v.im;
         }
     }
@@ -642,12 +644,17 @@ __global__ __launch_bounds__(kBlock) void k_rho_dot(int N, int Rp, int Lr, const
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_p_update(int N, int Rp, int Lr, int init, ColState cs,
                                                      cpx<T> *rp, cpx<T> *r, cpx<T> *p, const cpx<T> *P,
-                                                     size_t ldk, unsigned long long *ctr) {
+                                                     size_t ldk, cpx<T> *ringT) {
+    // ringT (optional): the block's Lr x 64 tile of the (rescaled) r' is also
+    // written column-major through LDS, for the fused shift update
+    extern __shared__ unsigned char tile_raw[];
+    cpx<T> *tile = reinterpret_cast<cpx<T> *>(tile_raw);
     ELEM_LOOP_BEGIN
-    if (cs.done[col]) return;
+    const bool active = !cs.done[col];
     const int sw = init ? 2 : cs.sw[col];
     const cpx<T> beta = ccast<T>(cs.beta_prev[col]);
-    if (sw == 1) {
+    const int tl = Lr + 1;
+    if (active && sw == 1) {
         const c128 cc = cs.swc[col];
         const c128 inv = cdiv(c128{1.0, 0.0}, cc);
         const cpx<T> ci = ccast<T>(inv);
@@ -658,17 +665,30 @@ __global__ __launch_bounds__(kBlock) void k_p_update(int N, int Rp, int Lr, int 
             rp[e] = v;
             r[e] = ci * r[e];
             p[e] = v + beta * Ps[i];
+            if (ringT) tile[lane * tl + (i - i0)] = v;
         }
-    } else if (sw == 2) {
+    } else if (active && sw == 2) {
         for (int i = i0 + wv; i < i1; i += kWavesPerBlock) {
             const size_t e = static_cast<size_t>(i) * Rp + col;
-            p[e] = rp[e];
+            const cpx<T> v = rp[e];
+            p[e] = v;
+            if (ringT) tile[lane * tl + (i - i0)] = v;
         }
-    } else {
+    } else if (active) {
         for (int i = i0 + wv; i < i1; i += kWavesPerBlock) {
             const size_t e = static_cast<size_t>(i) * Rp + col;
-            p[e] = rp[e] + beta * p[e];
+            const cpx<T> v = rp[e];
+            p[e] = v + beta * p[e];
+            if (ringT) tile[lane * tl + (i - i0)] = v;
         }
+    }
+    if (ringT == nullptr) return;
+    __syncthreads();
+    const int rows = i1 - i0;
+    const int c0 = cx * 64;
+    for (int t = threadIdx.x; t < 64 * rows; t += kBlock) {
+        const int c = t / rows, row = t % rows;
+        ringT[static_cast<size_t>(c0 + c) * N + i0 + row] = tile[c * tl + row];
     }
 }
 
@@ -1475,7 +1495,7 @@ template <typename T> class TileSolver {
         k_ctrl<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.Gs, n, 0, t_.part_c.get(), cs, ss);
         proj_update(cs, ss, 0, rp);
         k_update_r<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_alpha.get(), t_.q.get(),
-                                         t_.r.get(), t_.res.get(), t_.d.get(), t_.part_d.get(), nullptr);
+                                         t_.r.get(), t_.res.get(), t_.d.get(), t_.part_d.get(), cheb_ok_ ? 0 : 1);
         k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 0, inner_tol_, cs);
         inner_solve_cheb(o, cs, rp);
         k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), rp, t_.r.get(),
@@ -1536,7 +1556,7 @@ template <typename T> class TileSolver {
             prof_.begin(st_, KP_UPDATE_R, 0.0);
             k_update_r<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_alpha.get(),
                                              t_.q.get(), t_.r.get(), t_.res.get(), t_.d.get(), t_.part_d.get(),
-                                             ctr(KP_UPDATE_R));
+                                             cheb_ok_ ? 0 : 1);
             prof_.end(st_);
             k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 0, inner_tol, cs);
             inner_solve(o, cs, rp_next);
@@ -1554,12 +1574,16 @@ template <typename T> class TileSolver {
                 flush(cs, ss, n0, n + 1, 1, s.switched);
                 k_mark_applied<<<cb, 256, 0, st_>>>(td.Rp, n + 1, cs);
             }
+            // the seed update also writes the column-major copy of r' (after
+            // its switch rescale) when one block's row tile fits LDS
+            const bool fuse_t = full_ && td.Lr <= 64;
+            const size_t tshm = fuse_t ? 64 * static_cast<size_t>(td.Lr + 1) * sizeof(cpx<T>) : 0;
             prof_.begin(st_, KP_P_UPDATE, 0.0);
-            k_p_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, 0, cs, rp_next, t_.r.get(), t_.p.get(),
-                                             t_.P.get(), t_.ldk, ctr(KP_P_UPDATE));
+            k_p_update<T><<<eg, eb, tshm, st_>>>(td.N, td.Rp, td.Lr, 0, cs, rp_next, t_.r.get(), t_.p.get(),
+                                                t_.P.get(), t_.ldk,
+                                                fuse_t ? t_.ringT.get() + slot_next * NR : nullptr);
             prof_.end(st_);
-            if (full_) {
-                // after the switch rescale of r' in k_p_update
+            if (full_ && !fuse_t) {
                 prof_.begin(st_, KP_RING_T, 0.0);
                 k_ring_transpose<T><<<dim3(td.Rp / 64, div_up(td.N, 32)), kBlock, 0, st_>>>(
                     td.N, td.Rp, rp_next, t_.ringT.get() + slot_next * NR);
@@ -1784,10 +1808,11 @@ template <typename T> class TileSolver {
         const double solves = s_it + td.R;
         const double vec = static_cast<double>(td.N) * sizeof(cpx<T>);
         prof_.add_bytes(KP_SPMM_SEED, s_it * vec * 2);
-        prof_.add_bytes(KP_UPDATE_R, s_it * vec * 5);
+        prof_.add_bytes(KP_UPDATE_R, s_it * vec * (cheb_ok_ ? 3 : 5));
         prof_.add_bytes(KP_RHO_DOT, solves * vec * 2);
-        prof_.add_bytes(KP_P_UPDATE, solves * vec * 3);
-        if (full_) prof_.add_bytes(KP_RING_T, solves * vec * 2);
+        const bool fused_t = full_ && td.Lr <= 64;
+        prof_.add_bytes(KP_P_UPDATE, solves * vec * (fused_t ? 4 : 3));
+        if (full_ && !fused_t) prof_.add_bytes(KP_RING_T, solves * vec * 2);
         double fb = 0;
         for (const auto &f : flushes_) {
             const int n0 = f[0], n1 = f[1], nsw = f[2];
