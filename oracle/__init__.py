@@ -15,5 +15,7 @@ Modules:
                 projected carry with collinear restart, z-derivative carry)
   lanczos       the generalised Lanczos process (Sec. 3.2) and the continued
                 fraction of G_jj(z)
+  csc           the charge-self-consistent term (Sec. 2.2, eq. Hap-CSC) and
+                the self-consistency loop
 """
-from . import ased, green, spectral, shifted_cocg, lanczos  # noqa: F401
+from . import ased, green, spectral, shifted_cocg, lanczos, csc  # noqa: F401
