@@ -120,6 +120,44 @@ def lanczos_compare(ctx, cfg):
             "rel_diff_G_jj": float(np.abs(g1 - g2).max() / np.abs(g2).max())}
 
 
+def scc_measure(ctx):
+    """Charge self-consistency (eq. Hap-CSC): a converging small water box end
+    to end, and the cost of one iteration (charges of every orbital by the
+    projected solve + CSC update) on a larger box.  The Fermi level sits
+    mid-gap of the neutral system (from the oracle's spectrum of the small
+    box; the larger box uses the same value)."""
+    import numpy as np
+    import torch
+
+    from oracle import ased as oased, spectral as ospec
+    from paper_1002_1202_amd import api
+    from synth import configs
+    from synth.csc import hubbard_u
+    from synth.grids import shift_grid, trapezoid_weights
+
+    out = {}
+    small = configs.water_small(n_mol=8, n_rhs=4)["system"]
+    S, H0, _ = oased.dense_pair(small)
+    ev, _ = ospec.eig_pencil(H0, S)
+    nocc = int(round(small.valence.sum() / 2))
+    ef = 0.5 * (ev[nocc - 1] + ev[nocc])
+    z = shift_grid(-60.0, ef, 128, 0.5)
+    w = trapezoid_weights(z)
+    for name, n_mol, iters in (("water8", 8, 200), ("water256", 256, 3)):
+        s = small if n_mol == 8 else configs.water_small(n_mol=n_mol, n_rhs=4)["system"]
+        pair, _ = api.pair_from_system(ctx, s)
+        cs = api.Csc(ctx, pair, s, hubbard_u(s))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = cs.scc(pair, z, w, s.valence, beta=0.2, history=4, scc_tol=1e-9, max_iter=iters, tol=1e-10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"atoms": int(s.n_atoms), "N": int(s.n), "shifts": int(len(z)), "iterations": r["iterations"],
+                     "residual": r["residual"], "seconds": dt, "seconds_per_iteration": dt / r["iterations"],
+                     "converged": r["status"] == 0}
+    return out
+
+
 def batched_compare(ctx):
     """Mixed-precision batched solve vs the plain FP64 batched solve at tol
     1e-6 on the 32-system workload (G_jj, charges, band-energy terms), with
@@ -192,6 +230,7 @@ def main():
                     help="time the candidate launch shapes on this problem first and use the fastest")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-lanczos", action="store_true")
+    ap.add_argument("--no-scc", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a copy-like kernel over 1 GiB first (torch.neg: 1 GiB read, 1 GiB written), "
                          "which calibrates the HBM byte counters of a --pmc run")
@@ -314,6 +353,9 @@ def main():
         line["lanczos"] = lanczos_compare(ctx, cfg)
         print(f"lanczos: {line['lanczos']['lanczos']['seconds']:.3f} s vs projected COCG "
               f"{line['lanczos']['cocg_projected']['seconds']:.3f} s", file=sys.stderr, flush=True)
+    if not args.no_scc:
+        line["scc"] = scc_measure(ctx)
+        print(f"scc: {line['scc']}", file=sys.stderr, flush=True)
     if not args.no_batched:
         line["batched"] = batched_compare(ctx)
     if not args.no_cpu_baseline:

@@ -244,6 +244,48 @@ gsc_status gsc_lanczos_green(gsc_ctx *ctx, const gsc_pair *pair, int nshift, con
                              const gsc_opts *opts, double *G_diag, double *coef_a, double *coef_b,
                              int *steps, int out_mem, gsc_stats *stats);
 
+/* ---- charge self-consistency (Sec. 2.2, eq. Hap-CSC) --------------------- */
+/*   H^CSC_{ia,jb} = 1/2 S_{ia,jb} sum_k (gamma_ik + gamma_jk) dq_k
+ *                 = 1/2 S_{ia,jb} (V_i + V_j),   V = gamma dq,
+ * dq_k = Mulliken electron count of atom k minus its valence.  gamma (the
+ * paper does not give it): on the atom pairs the pair's block pattern
+ * couples (every atom of block row I with every atom of block column J,
+ * displaced by that block's translation), gamma_ii = U_i for an atom with
+ * itself, else e^2 / sqrt(r^2 + a^2) with a = e^2 (1/U_i + 1/U_k) / 2 and
+ * e^2 = 14.399645 eV A (Klopman-Ohno). */
+typedef struct gsc_csc gsc_csc;
+/* geom: positions, orb_atom and block translations as for gsc_ased_build
+ * (HOST); hubbard_u HOST [n_atoms], > 0 (eV).  The handle keeps device
+ * copies and gamma; it belongs to the pair's context and device. */
+gsc_status gsc_csc_create(gsc_ctx *ctx, const gsc_pair *pair, const gsc_ased_geom *geom, const double *hubbard_u,
+                          gsc_csc **out);
+void gsc_csc_destroy(gsc_csc *csc);
+/* V = gamma dq; dq, V [n_atoms] per mem. */
+gsc_status gsc_csc_potential(gsc_csc *csc, const double *dq, double *V, int mem);
+/* The pair's H values become H0 + H^CSC(dq) on every stored entry (S of
+ * the pair); H0 [nnzb][B][B] and dq [n_atoms] per mem. */
+gsc_status gsc_csc_hamiltonian(gsc_csc *csc, gsc_pair *pair, const double *H0, const double *dq, int mem);
+/* Self-consistency loop.  H0 is the pair's H at entry.  Each iteration sets
+ * H = H0 + H^CSC(dq_in), computes the Mulliken charges of every orbital with
+ * the shifts z and weights w (HOST [nshift]) by the projected shifted solve,
+ * dq_out = atom sums - valence (HOST [n_atoms]); it stops when
+ * max |dq_out - dq_in| <= tol, else takes the next dq_in by Anderson mixing
+ * of the last `history` residuals with step beta (history 0: linear mixing
+ * dq_in += beta (dq_out - dq_in)).  dq: HOST [n_atoms], the starting charges
+ * on entry and the last dq_in on exit; q_orb HOST [N] (the last charges) and
+ * e_band HOST may be NULL.  On exit the pair holds H0 + H^CSC(dq).
+ * GSC_NOT_CONVERGED after max_iter iterations (outputs written). */
+typedef struct {
+    double beta;          /* [0.2]  mixing step                            */
+    int history;          /* [4]    Anderson history (0 = linear mixing)    */
+    double tol;           /* [1e-8] max |dq_out - dq_in| to stop            */
+    int max_iter;         /* [100]                                          */
+} gsc_scc_opts;
+void gsc_scc_opts_default(gsc_scc_opts *o);
+gsc_status gsc_scc(gsc_ctx *ctx, gsc_csc *csc, gsc_pair *pair, int nshift, const double *z, const double *w,
+                   const double *valence, const gsc_scc_opts *sopts, const gsc_opts *opts, double *dq, double *q_orb,
+                   double *e_band, int *iters, double *residual);
+
 /* Mulliken charge and band energy per orbital a = orb_idx[r] (Sec. 2.2),
  * spin 2, quadrature weights w[k] (HOST) over E_k = Re z_k:
  *   q_a = -(2/pi) sum_k w_k Im[(S G_k)_aa],

@@ -318,6 +318,62 @@ def mulliken_band(ctx: Context, pair: Pair, z, w, orb, **opt):
     return q, e, eb.value, info
 
 
+class Csc:
+    """Charge-self-consistent term on a pair's pattern (Sec. 2.2, eq.
+    Hap-CSC): gamma on the coupled atom pairs for the geometry of
+    ``system`` and on-site hardness ``U`` (eV, one per atom)."""
+
+    def __init__(self, ctx: Context, pair: Pair, system, U, positions=None):
+        self.ctx = ctx
+        self.n_atoms = int(system.n_atoms)
+        geom = AsedGeometry(system, positions)
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        h = C.c_void_p()
+        L.check(ctx.lib.gsc_csc_create(ctx.h, pair.h, C.byref(geom.struct), _ptr(U), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.gsc_csc_destroy(self.h)
+            self.h = None
+
+    def potential(self, dq):
+        """V = gamma dq (host arrays)."""
+        dq = np.ascontiguousarray(dq, dtype=np.float64)
+        V = np.empty(self.n_atoms)
+        L.check(self.ctx.lib.gsc_csc_potential(self.h, _vp(dq), _vp(V), L.MEM_HOST))
+        return V
+
+    def hamiltonian(self, pair: Pair, H0, dq):
+        """Set the pair's H to H0 + H^CSC(dq); H0 (nnzb, B, B) host or device."""
+        mem = L.MEM_DEVICE if _is_device(H0) else L.MEM_HOST
+        if mem == L.MEM_HOST:
+            H0 = np.ascontiguousarray(H0, dtype=np.float64)
+            dq = np.ascontiguousarray(dq, dtype=np.float64)
+        L.check(self.ctx.lib.gsc_csc_hamiltonian(self.h, pair.h, _vp(H0), _vp(dq), mem))
+
+    def scc(self, pair: Pair, z, w, valence, dq0=None, beta=0.2, history=4, scc_tol=1e-8, max_iter=100, **opt):
+        """Self-consistency loop (Anderson mixing) to max |dq_out - dq_in| <=
+        scc_tol; ``opt`` are the solver options of each charge evaluation.
+        Returns a dict with dq, q_orb, e_band, iterations, residual and
+        status; the pair keeps H0 + H^CSC(dq)."""
+        z = np.ascontiguousarray(z, dtype=np.complex128)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        valence = np.ascontiguousarray(valence, dtype=np.float64)
+        dq = np.zeros(self.n_atoms) if dq0 is None else np.array(dq0, dtype=np.float64)
+        q = np.empty(pair.n)
+        so = L.SccOpts(beta, history, scc_tol, max_iter)
+        opts = make_opts(**opt)
+        eb = C.c_double()
+        it = C.c_int()
+        res = C.c_double()
+        status = self.ctx.lib.gsc_scc(self.ctx.h, self.h, pair.h, z.shape[0], _ptr(_complex_view(z)), _ptr(w),
+                                      _ptr(valence), C.byref(so), C.byref(opts), _ptr(dq), _ptr(q), C.byref(eb),
+                                      C.byref(it), C.byref(res))
+        L.check(status)
+        return dict(dq=dq, q_orb=q, e_band=eb.value, iterations=it.value, residual=res.value, status=status)
+
+
 @dataclass
 class LanczosResult:
     G_diag: object          # [K][R] complex128 (numpy or torch device tensor)

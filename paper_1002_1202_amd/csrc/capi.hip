@@ -5,12 +5,14 @@
 #include <cstring>
 #include <memory>
 
+#include "csc.h"
 #include "pair.h"
 #include "solver.h"
 #include "spmm.h"
 
 struct gsc_ctx { gsc::Ctx c; };
 struct gsc_pair { gsc::Pair p; };
+struct gsc_csc { gsc::Csc c; };
 
 namespace gsc {
 
@@ -409,6 +411,187 @@ gsc_status gsc_lanczos_green(gsc_ctx *ctx, const gsc_pair *pair, int nshift, con
         req.out_mem = out_mem;
         req.stats = stats;
         return run_lanczos(ctx->c, req);
+    });
+}
+
+gsc_status gsc_csc_create(gsc_ctx *ctx, const gsc_pair *pair, const gsc_ased_geom *geom, const double *hubbard_u,
+                          gsc_csc **out) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr && pair != nullptr && geom != nullptr && out != nullptr,
+                    "ctx/pair/geom/out must not be NULL");
+        GSC_REQUIRE(hubbard_u != nullptr, "hubbard_u must not be NULL");
+        GSC_REQUIRE(geom->n_atoms >= 1 && geom->pos && geom->orb_atom && geom->trans, "incomplete geometry");
+        for (int64_t a = 0; a < geom->n_atoms; ++a)
+            GSC_REQUIRE(hubbard_u[a] > 0.0 && std::isfinite(hubbard_u[a]), "hubbard_u must be positive");
+        DeviceGuard g(ctx->c.device);
+        auto h = std::make_unique<gsc_csc>();
+        csc_build(h->c, ctx->c, pair->p, *geom, hubbard_u);
+        *out = h.release();
+        return GSC_OK;
+    });
+}
+
+void gsc_csc_destroy(gsc_csc *csc) {
+    if (csc == nullptr) return;
+    DeviceGuard g(csc->c.ctx->device);
+    delete csc;
+}
+
+gsc_status gsc_csc_potential(gsc_csc *csc, const double *dq, double *V, int mem) {
+    return guarded([&] {
+        GSC_REQUIRE(csc != nullptr && dq != nullptr && V != nullptr, "csc/dq/V must not be NULL");
+        DeviceGuard g(csc->c.ctx->device);
+        hipStream_t st = csc->c.ctx->stream;
+        const size_t n = static_cast<size_t>(csc->c.n_atoms);
+        if (mem == GSC_MEM_DEVICE) {
+            csc_potential(csc->c, dq, V, st);
+            GSC_HIP(hipStreamSynchronize(st));
+            return GSC_OK;
+        }
+        DevBuf<double> d(n), v(n);
+        GSC_HIP(hipMemcpyAsync(d.get(), dq, n * 8, hipMemcpyHostToDevice, st));
+        csc_potential(csc->c, d.get(), v.get(), st);
+        GSC_HIP(hipMemcpyAsync(V, v.get(), n * 8, hipMemcpyDeviceToHost, st));
+        GSC_HIP(hipStreamSynchronize(st));
+        return GSC_OK;
+    });
+}
+
+gsc_status gsc_csc_hamiltonian(gsc_csc *csc, gsc_pair *pair, const double *H0, const double *dq, int mem) {
+    return guarded([&] {
+        GSC_REQUIRE(csc != nullptr && pair != nullptr && H0 != nullptr && dq != nullptr, "NULL argument");
+        Pair &p = pair->p;
+        GSC_REQUIRE(p.nnzb == csc->c.nnzb && p.B == csc->c.B, "the pair does not match the csc handle");
+        DeviceGuard g(csc->c.ctx->device);
+        hipStream_t st = csc->c.ctx->stream;
+        const size_t n = static_cast<size_t>(csc->c.n_atoms), nv = static_cast<size_t>(p.nnzb) * p.B * p.B;
+        DevBuf<double> d, h0, v(n);
+        const double *dd = dq, *hh = H0;
+        if (mem != GSC_MEM_DEVICE) {
+            d.alloc(n);
+            h0.alloc(nv);
+            GSC_HIP(hipMemcpyAsync(d.get(), dq, n * 8, hipMemcpyHostToDevice, st));
+            GSC_HIP(hipMemcpyAsync(h0.get(), H0, nv * 8, hipMemcpyHostToDevice, st));
+            dd = d.get();
+            hh = h0.get();
+        }
+        csc_potential(csc->c, dd, v.get(), st);
+        csc_hamiltonian(csc->c, p, hh, v.get(), st);
+        GSC_HIP(hipStreamSynchronize(st));
+        return GSC_OK;
+    });
+}
+
+void gsc_scc_opts_default(gsc_scc_opts *o) {
+    if (o == nullptr) return;
+    o->beta = 0.2;
+    o->history = 4;
+    o->tol = 1e-8;
+    o->max_iter = 100;
+}
+
+gsc_status gsc_scc(gsc_ctx *ctx, gsc_csc *csc, gsc_pair *pair, int nshift, const double *z, const double *w,
+                   const double *valence, const gsc_scc_opts *sopts, const gsc_opts *opts, double *dq, double *q_orb,
+                   double *e_band, int *iters, double *residual) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr && csc != nullptr && pair != nullptr, "ctx/csc/pair must not be NULL");
+        GSC_REQUIRE(w != nullptr && valence != nullptr && dq != nullptr, "w/valence/dq must not be NULL");
+        gsc_scc_opts so;
+        gsc_scc_opts_default(&so);
+        if (sopts) so = *sopts;
+        GSC_REQUIRE(so.beta > 0.0 && so.history >= 0 && so.history <= 16 && so.tol > 0.0 && so.max_iter >= 1,
+                    "invalid scc options");
+        gsc_opts o;
+        gsc_opts_default(&o);
+        if (opts) o = *opts;
+        o.carry = GSC_CARRY_PROJECTED;
+        validate_opts(o);
+        validate_shifts(nshift, z, o.seed_index);
+        Pair &p = pair->p;
+        Csc &c = csc->c;
+        GSC_REQUIRE(p.nnzb == c.nnzb && p.B == c.B, "the pair does not match the csc handle");
+        DeviceGuard g(ctx->c.device);
+        hipStream_t st = ctx->c.stream;
+        const int64_t na = c.n_atoms, N = p.n;
+        const int m = so.history;
+        const size_t nv = static_cast<size_t>(p.nnzb) * p.B * p.B;
+        DevBuf<double> H0(nv), din(na), dout(na), f(na), V(na), xnew(na), qorb(N), Z(na), mx(1);
+        DevBuf<double> Xh(std::max<int64_t>(1, m * na)), Fh(std::max<int64_t>(1, m * na)), dots(m * m + m + 1),
+            gdev(m + 1);
+        GSC_HIP(hipMemcpyAsync(H0.get(), p.H.get(), nv * 8, hipMemcpyDeviceToDevice, st));
+        GSC_HIP(hipMemcpyAsync(din.get(), dq, na * 8, hipMemcpyHostToDevice, st));
+        GSC_HIP(hipMemcpyAsync(Z.get(), valence, na * 8, hipMemcpyHostToDevice, st));
+        std::vector<int64_t> orbs(N);
+        for (int64_t i = 0; i < N; ++i) orbs[i] = i;
+        int it = 0, stored = 0;
+        double res = 0.0, eb = 0.0;
+        for (it = 1; it <= so.max_iter; ++it) {
+            csc_potential(c, din.get(), V.get(), st);
+            csc_hamiltonian(c, p, H0.get(), V.get(), st);
+            const gsc_status s = gsc_mulliken_band(ctx, pair, nshift, z, w, static_cast<int>(N), orbs.data(), &o,
+                                                   qorb.get(), nullptr, &eb, GSC_MEM_DEVICE, nullptr);
+            if (s < 0) return s;
+            csc_charges(c, qorb.get(), Z.get(), din.get(), dout.get(), f.get(), st);
+            max_abs(na, f.get(), mx.get(), st);
+            GSC_HIP(hipMemcpyAsync(&res, mx.get(), 8, hipMemcpyDeviceToHost, st));
+            GSC_HIP(hipStreamSynchronize(st));
+            GSC_REQUIRE(std::isfinite(res), "non-finite charges in the self-consistency loop");
+            if (res <= so.tol) break;
+            const int mh = std::min(stored, m);
+            std::vector<double> gh(std::max(mh, 1), 0.0);
+            if (mh > 0) {
+                anderson_dots(na, mh, f.get(), Fh.get(), dots.get(), st);
+                std::vector<double> hd(mh * mh + mh);
+                GSC_HIP(hipMemcpyAsync(hd.data(), dots.get(), hd.size() * 8, hipMemcpyDeviceToHost, st));
+                GSC_HIP(hipStreamSynchronize(st));
+                // normal equations of min |f - dF g| (mh <= 16), Gaussian elimination with pivoting
+                std::vector<double> A(hd.begin(), hd.begin() + mh * mh), rhs(hd.begin() + mh * mh, hd.end());
+                double tr = 0.0;
+                for (int i = 0; i < mh; ++i) tr += A[i * mh + i];
+                for (int i = 0; i < mh; ++i) A[i * mh + i] += 1e-14 * tr + 1e-300;
+                for (int col = 0; col < mh; ++col) {
+                    int piv = col;
+                    for (int r = col + 1; r < mh; ++r)
+                        if (std::fabs(A[r * mh + col]) > std::fabs(A[piv * mh + col])) piv = r;
+                    for (int k = 0; k < mh; ++k) std::swap(A[col * mh + k], A[piv * mh + k]);
+                    std::swap(rhs[col], rhs[piv]);
+                    for (int r = col + 1; r < mh; ++r) {
+                        const double fct = A[r * mh + col] / A[col * mh + col];
+                        for (int k = col; k < mh; ++k) A[r * mh + k] -= fct * A[col * mh + k];
+                        rhs[r] -= fct * rhs[col];
+                    }
+                }
+                for (int r = mh - 1; r >= 0; --r) {
+                    double v = rhs[r];
+                    for (int k = r + 1; k < mh; ++k) v -= A[r * mh + k] * gh[k];
+                    gh[r] = v / A[r * mh + r];
+                }
+                GSC_HIP(hipMemcpyAsync(gdev.get(), gh.data(), mh * 8, hipMemcpyHostToDevice, st));
+            }
+            anderson_mix(na, mh, so.beta, gdev.get(), din.get(), f.get(), Xh.get(), Fh.get(), xnew.get(), st);
+            if (m > 0) {
+                const int slot = stored % m;
+                GSC_HIP(hipMemcpyAsync(Xh.get() + static_cast<size_t>(slot) * na, din.get(), na * 8,
+                                       hipMemcpyDeviceToDevice, st));
+                GSC_HIP(hipMemcpyAsync(Fh.get() + static_cast<size_t>(slot) * na, f.get(), na * 8,
+                                       hipMemcpyDeviceToDevice, st));
+                ++stored;
+            }
+            GSC_HIP(hipMemcpyAsync(din.get(), xnew.get(), na * 8, hipMemcpyDeviceToDevice, st));
+        }
+        const bool conv = it <= so.max_iter;
+        if (!conv) {
+            // the pair holds H0 + H^CSC of the last input charges
+            csc_potential(c, din.get(), V.get(), st);
+            csc_hamiltonian(c, p, H0.get(), V.get(), st);
+        }
+        GSC_HIP(hipMemcpyAsync(dq, din.get(), na * 8, hipMemcpyDeviceToHost, st));
+        if (q_orb) GSC_HIP(hipMemcpyAsync(q_orb, qorb.get(), N * 8, hipMemcpyDeviceToHost, st));
+        GSC_HIP(hipStreamSynchronize(st));
+        if (e_band) *e_band = eb;
+        if (iters) *iters = conv ? it : so.max_iter;
+        if (residual) *residual = res;
+        return conv ? GSC_OK : GSC_NOT_CONVERGED;
     });
 }
 
