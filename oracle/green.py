@@ -102,6 +102,32 @@ def band_energy_grad_dense(H, S, z, w):
     return gH, gS
 
 
+def charge_grad_dense(H, S, z, w, orbs, qbar):
+    """Dense gradients (N x N) of L = sum_r qbar_r q_{orbs[r]} with respect to
+    every entry of H and S, each entry an independent variable.
+
+    From q_a = -(2/pi) sum_k w_k Im[(S G_k)_aa] and dG = G dH G,
+    dG = -z G dS G (G = (zS - H)^{-1}, complex symmetric):
+        d(S G)_aa / dH_bc = (S G)_ab G_ca,
+        d(S G)_aa / dS_bc = delta_ab G_ca - z (S G)_ab G_ca,
+    so with Q = diag(qbar on the listed orbitals)
+        dL/dH = -(2/pi) sum_k w_k Im[G_k S Q G_k],
+        dL/dS = -(2/pi) sum_k w_k Im[Q G_k - z_k G_k S Q G_k].
+    (With Q = I and weights w_k E_k this is the band-energy gradient.)"""
+    z = np.asarray(z, dtype=np.complex128)
+    n = H.shape[0]
+    Q = np.zeros((n, n))
+    np.add.at(Q, (np.asarray(orbs), np.asarray(orbs)), np.asarray(qbar, dtype=np.float64))
+    gH = np.zeros((n, n))
+    gS = np.zeros((n, n))
+    for zk, wk in zip(z, w):
+        G = np.linalg.inv(zk * S - H)
+        GSQG = G @ S @ Q @ G
+        gH += -(2.0 / np.pi) * wk * GSQG.imag
+        gS += -(2.0 / np.pi) * wk * (Q @ G - zk * GSQG).imag
+    return gH, gS
+
+
 def true_residual(H, S, z, X, rhs_idx=None, B_dense=None):
     """||b - (z_k S - H) x_k||_2 / ||b||_2 for every (k, r)."""
     n = H.shape[0]
