@@ -158,6 +158,36 @@ def scc_measure(ctx):
     return out
 
 
+def charge_vjp_measure(ctx):
+    """Gradient of a charge loss on every orbital of a 64-molecule water box
+    (two full-carry solves per orbital + the pattern contraction), next to
+    the band-energy backward on the same system (z-derivative carry); with
+    qbar = 1 and weights w E the two give the same gradient."""
+    import numpy as np
+    import torch
+
+    from paper_1002_1202_amd import api
+    from synth import configs
+
+    c = configs.water_small(n_mol=64, n_rhs=4, n_shift=64, eta=0.2)
+    s, z = c["system"], c["z"]
+    w = np.full(len(z), (z[-1].real - z[0].real) / (len(z) - 1))
+    pair, _ = api.pair_from_system(ctx, s)
+    orbs = np.arange(s.n)
+    out = {"workload": f"water64: N={s.n}, {len(z)} shifts, all orbitals, tol 1e-10"}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dH, dS, _ = api.charge_vjp(ctx, pair, z, w * z.real, orbs, np.ones(s.n))
+    torch.cuda.synchronize()
+    out["charge_vjp_seconds"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    eH, eS, _, _ = api.band_energy_vjp(ctx, pair, z, w)
+    torch.cuda.synchronize()
+    out["band_energy_vjp_seconds"] = time.perf_counter() - t0
+    out["rel_diff"] = float(max(np.abs(dH - eH).max() / np.abs(eH).max(), np.abs(dS - eS).max() / np.abs(eS).max()))
+    return out
+
+
 def batched_compare(ctx):
     """Mixed-precision batched solve vs the plain FP64 batched solve at tol
     1e-6 on the 32-system workload (G_jj, charges, band-energy terms), with
@@ -231,6 +261,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-lanczos", action="store_true")
     ap.add_argument("--no-scc", action="store_true")
+    ap.add_argument("--no-charge-vjp", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a copy-like kernel over 1 GiB first (torch.neg: 1 GiB read, 1 GiB written), "
                          "which calibrates the HBM byte counters of a --pmc run")
@@ -356,6 +387,9 @@ def main():
     if not args.no_scc:
         line["scc"] = scc_measure(ctx)
         print(f"scc: {line['scc']}", file=sys.stderr, flush=True)
+    if not args.no_charge_vjp:
+        line["charge_vjp"] = charge_vjp_measure(ctx)
+        print(f"charge_vjp: {line['charge_vjp']}", file=sys.stderr, flush=True)
     if not args.no_batched:
         line["batched"] = batched_compare(ctx)
     if not args.no_cpu_baseline:

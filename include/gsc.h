@@ -244,6 +244,20 @@ gsc_status gsc_lanczos_green(gsc_ctx *ctx, const gsc_pair *pair, int nshift, con
                              const gsc_opts *opts, double *G_diag, double *coef_a, double *coef_b,
                              int *steps, int out_mem, gsc_stats *stats);
 
+/* Gradient of a loss of the Mulliken charges, L = sum_r qbar[r] q_{orb_idx[r]}
+ * (Sec. 2.2), on every stored entry of H and S (each an independent
+ * variable), accumulated into dHval, dSval ([nnzb][B][B] per mem):
+ *   dL/dH = -(2/pi) sum_k w_k Im[G_k S Q G_k],
+ *   dL/dS = -(2/pi) sum_k w_k Im[Q G_k - z_k G_k S Q G_k],   Q = diag(qbar).
+ * For every listed orbital a the shifted solver runs twice (full carry):
+ * x = G_k e_a and lam = G_k S e_a, combined on the pattern.  Memory
+ * 2 nshift N x (orbitals per tile) complex; for small and medium systems.
+ * z, w, orb_idx, qbar HOST.  GSC_NOT_CONVERGED if a solve did not converge
+ * (gradients still written). */
+gsc_status gsc_charge_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const double *z, const double *w,
+                          int norb, const int64_t *orb_idx, const double *qbar, const gsc_opts *opts,
+                          double *dHval, double *dSval, int mem, gsc_stats *stats);
+
 /* ---- charge self-consistency (Sec. 2.2, eq. Hap-CSC) --------------------- */
 /*   H^CSC_{ia,jb} = 1/2 S_{ia,jb} sum_k (gamma_ik + gamma_jk) dq_k
  *                 = 1/2 S_{ia,jb} (V_i + V_j),   V = gamma dq,

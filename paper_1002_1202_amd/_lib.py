@@ -76,6 +76,8 @@ SIGNATURES = {
     "gsc_band_energy_vjp": (C.c_int, [_VP, _VP, C.c_int, _DP, _DP, C.c_double, C.POINTER(Opts),
                                       _VP, _VP, _DP, C.c_int, C.POINTER(Stats)]),
     "gsc_solve_batched": (C.c_int, [_VP, C.c_int, C.POINTER(Problem), C.POINTER(Opts)]),
+    "gsc_charge_vjp": (C.c_int, [_VP, _VP, C.c_int, _DP, _DP, C.c_int, _I64P, _DP, C.POINTER(Opts), _VP, _VP,
+                                 C.c_int, C.POINTER(Stats)]),
     "gsc_csc_create": (C.c_int, [_VP, _VP, C.POINTER(AsedGeom), _DP, C.POINTER(C.c_void_p)]),
     "gsc_csc_destroy": (None, [_VP]),
     "gsc_csc_potential": (C.c_int, [_VP, _VP, _VP, C.c_int]),

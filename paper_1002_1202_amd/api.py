@@ -318,6 +318,30 @@ def mulliken_band(ctx: Context, pair: Pair, z, w, orb, **opt):
     return q, e, eb.value, info
 
 
+def charge_vjp(ctx: Context, pair: Pair, z, w, orbs, qbar, dH=None, dS=None, **opt):
+    """Gradients of L = sum_r qbar[r] q_{orbs[r]} (Mulliken charges) on the
+    stored entries: dH += dL/dH_bc, dS += dL/dS_bc (zeros when not given;
+    numpy or torch device tensors of shape (nnzb, B, B)).  Returns (dH, dS,
+    status)."""
+    z = np.ascontiguousarray(z, dtype=np.complex128)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    orbs = np.ascontiguousarray(orbs, dtype=np.int64)
+    qbar = np.ascontiguousarray(qbar, dtype=np.float64)
+    shape = (pair.nnzb, pair.block, pair.block)
+    if dH is None:
+        dH = np.zeros(shape)
+    if dS is None:
+        dS = np.zeros(shape)
+    mem = L.MEM_DEVICE if _is_device(dH) else L.MEM_HOST
+    opts = make_opts(**opt)
+    st = L.Stats()
+    status = ctx.lib.gsc_charge_vjp(ctx.h, pair.h, z.shape[0], _ptr(_complex_view(z)), _ptr(w), orbs.shape[0],
+                                    _ptr(orbs, C.c_int64), _ptr(qbar), C.byref(opts), _vp(dH), _vp(dS), mem,
+                                    C.byref(st))
+    L.check(status)
+    return dH, dS, status
+
+
 class Csc:
     """Charge-self-consistent term on a pair's pattern (Sec. 2.2, eq.
     Hap-CSC): gamma on the coupled atom pairs for the geometry of

@@ -414,6 +414,97 @@ gsc_status gsc_lanczos_green(gsc_ctx *ctx, const gsc_pair *pair, int nshift, con
     });
 }
 
+gsc_status gsc_charge_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const double *z, const double *w,
+                          int norb, const int64_t *orb_idx, const double *qbar, const gsc_opts *opts,
+                          double *dHval, double *dSval, int mem, gsc_stats *stats) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr && pair != nullptr, "ctx/pair must not be NULL");
+        GSC_REQUIRE(w != nullptr && qbar != nullptr && dHval != nullptr && dSval != nullptr, "NULL argument");
+        gsc_opts o;
+        gsc_opts_default(&o);
+        if (opts) o = *opts;
+        o.carry = GSC_CARRY_FULL;
+        validate_opts(o);
+        validate_shifts(nshift, z, o.seed_index);
+        const Pair &p = pair->p;
+        GSC_REQUIRE(norb >= 1 && orb_idx != nullptr, "need at least one orbital");
+        for (int r = 0; r < norb; ++r) GSC_REQUIRE(orb_idx[r] >= 0 && orb_idx[r] < p.n, "orbital index out of range");
+        DeviceGuard g(ctx->c.device);
+        hipStream_t st = ctx->c.stream;
+        const size_t nv = static_cast<size_t>(p.nnzb) * p.B * p.B;
+        DevBuf<double> dH, dS;
+        double *gH = dHval, *gS = dSval;
+        if (mem != GSC_MEM_DEVICE) {
+            dH.alloc(nv);
+            dS.alloc(nv);
+            GSC_HIP(hipMemcpyAsync(dH.get(), dHval, nv * 8, hipMemcpyHostToDevice, st));
+            GSC_HIP(hipMemcpyAsync(dS.get(), dSval, nv * 8, hipMemcpyHostToDevice, st));
+            gH = dH.get();
+            gS = dS.get();
+        }
+        DevBuf<c128> dz(nshift);
+        DevBuf<double> dw(nshift);
+        GSC_HIP(hipMemcpyAsync(dz.get(), z, nshift * sizeof(c128), hipMemcpyHostToDevice, st));
+        GSC_HIP(hipMemcpyAsync(dw.get(), w, nshift * sizeof(double), hipMemcpyHostToDevice, st));
+        // orbitals per tile: two [K][R][N] complex solution sets in 40 % of free memory
+        size_t freeb = 0, totalb = 0;
+        GSC_HIP(hipMemGetInfo(&freeb, &totalb));
+        const double per = 2.0 * nshift * static_cast<double>(p.n) * sizeof(c128) + 16.0 * p.n * sizeof(c128);
+        int Rt = o.rhs_tile > 0 ? o.rhs_tile : static_cast<int>(0.4 * static_cast<double>(freeb) / per);
+        Rt = std::max(1, std::min(Rt, norb));
+        bool conv = true;
+        long long inner = 0, sri = 0;
+        int outer = 0;
+        for (int r0 = 0; r0 < norb; r0 += Rt) {
+            const int R = std::min(Rt, norb - r0);
+            DevBuf<int64_t> dorb(R);
+            DevBuf<double> dqb(R);
+            GSC_HIP(hipMemcpyAsync(dorb.get(), orb_idx + r0, R * sizeof(int64_t), hipMemcpyHostToDevice, st));
+            GSC_HIP(hipMemcpyAsync(dqb.get(), qbar + r0, R * sizeof(double), hipMemcpyHostToDevice, st));
+            DevBuf<c128> X(static_cast<size_t>(nshift) * R * p.n), Lm(static_cast<size_t>(nshift) * R * p.n);
+            DevBuf<c128> Bs(static_cast<size_t>(R) * p.n);
+            launch_s_columns(st, p, R, dorb.get(), Bs.get());
+            gsc_stats s1{}, s2{};
+            for (int pass = 0; pass < 2; ++pass) {
+                SolveRequest req;
+                req.pair = &p;
+                req.K = nshift;
+                req.z = z;
+                req.R = R;
+                req.opts = o;
+                req.out_mem = GSC_MEM_DEVICE;
+                req.stats = pass == 0 ? &s1 : &s2;
+                if (pass == 0) {
+                    req.rhs_idx = orb_idx + r0;
+                    req.G_cols = reinterpret_cast<double *>(X.get());
+                } else {
+                    req.B_dense = reinterpret_cast<const double *>(Bs.get());
+                    req.G_cols = reinterpret_cast<double *>(Lm.get());
+                }
+                const gsc_status s = run_solve(ctx->c, req);
+                if (s < 0) return s;
+                if (s == GSC_NOT_CONVERGED) conv = false;
+            }
+            launch_charge_vjp(st, p, nshift, R, X.get(), Lm.get(), dz.get(), dw.get(), dqb.get(), dorb.get(), gH, gS);
+            GSC_HIP(hipStreamSynchronize(st));
+            inner += s1.inner_iters + s2.inner_iters;
+            sri += s1.shift_rhs_iters + s2.shift_rhs_iters;
+            outer = std::max(outer, std::max(s1.outer_iters, s2.outer_iters));
+        }
+        if (mem != GSC_MEM_DEVICE) {
+            GSC_HIP(hipMemcpyAsync(dHval, gH, nv * 8, hipMemcpyDeviceToHost, st));
+            GSC_HIP(hipMemcpyAsync(dSval, gS, nv * 8, hipMemcpyDeviceToHost, st));
+        }
+        GSC_HIP(hipStreamSynchronize(st));
+        if (stats) {
+            stats->outer_iters = outer;
+            stats->inner_iters = inner;
+            stats->shift_rhs_iters = sri;
+        }
+        return conv ? GSC_OK : GSC_NOT_CONVERGED;
+    });
+}
+
 gsc_status gsc_csc_create(gsc_ctx *ctx, const gsc_pair *pair, const gsc_ased_geom *geom, const double *hubbard_u,
                           gsc_csc **out) {
     return guarded([&] {

@@ -34,4 +34,12 @@ void anderson_dots(int64_t n, int mh, const double *f, const double *Fh, double 
 void anderson_mix(int64_t n, int mh, double beta, const double *g, const double *x, const double *f,
                   const double *Xh, const double *Fh, double *xnew, hipStream_t st);
 
+// Gradient of a charge-dependent loss (charge_vjp.hip): columns S e_a of
+// the listed orbitals (out [R][N] complex) and the accumulation of dL/dH,
+// dL/dS on the stored entries from x = G_k e_a and lam = G_k S e_a
+// ([K][R][N] complex each).
+void launch_s_columns(hipStream_t st, const Pair &p, int R, const int64_t *orbs, c128 *out);
+void launch_charge_vjp(hipStream_t st, const Pair &p, int K, int R, const c128 *X, const c128 *Lm, const c128 *z,
+                       const double *w, const double *qbar, const int64_t *orbs, double *dH, double *dS);
+
 }  // namespace gsc
