@@ -58,3 +58,88 @@ def test_si4096_sampled_residuals_and_symmetry():
             sym = max(sym, float(np.abs(gij - gji).max() / scale_))
     print(f"  max |G_ij - G_ji| / max|G| = {sym:.2e}", flush=True)
     assert sym < 1e-9
+
+
+def test_slab8192_subset_band_energy_forces_fd():
+    """Si (001) slab at full size (8192 atoms, N = 32768, 512 shifts on
+    [-20, E_F]): the band-energy contribution of the orbitals of two surface
+    atoms, differentiated by the charge-loss adjoint and chained through the
+    ASED pair to forces, against central differences at 1e-4 A of the same
+    energy computed by forward solves (pattern, scale and angles fixed)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1002_1202_amd import api
+    cfg = configs.slab8192()
+    s, z, w = cfg["system"], cfg["z"], cfg["w"]
+    print(f"case: slab8192 full size N={s.n} K={len(z)}", flush=True)
+    ctx = api.Context(0)
+    pair, scale = api.pair_from_system(ctx, s)
+    top = np.argsort(s.positions[:, 2])[-2:]
+    orbs = np.concatenate([np.flatnonzero(s.orb_atom == a) for a in top]).astype(np.int64)
+    dH, dS, st = api.charge_vjp(ctx, pair, z, w * z.real, orbs, np.ones(len(orbs)), tol=1e-10)
+    assert st == 0
+    F = api.ased_vjp(ctx, pair, s, scale, dH, dS)
+    print(f"  |sum F| = {np.abs(F.sum(0)).max():.2e}, max |F| = {np.abs(F).max():.3e}", flush=True)
+
+    def energy(p):
+        api.ased_build(ctx, pair, s, scale, positions=p)
+        _, _, e, _ = api.mulliken_band(ctx, pair, z, w, orbs, tol=1e-12, carry="projected")
+        return e
+
+    h = cfg["fd_step"]
+    for atom, ax in [(int(top[0]), 0), (int(top[1]), 2)]:
+        e = []
+        for sgn in (1, -1):
+            p = s.positions.copy()
+            p[atom, ax] += sgn * h
+            e.append(energy(p))
+        fd = -(e[0] - e[1]) / (2 * h)
+        print(f"  atom {atom} ax {ax}: F={F[atom, ax]:.8e} fd={fd:.8e}", flush=True)
+        assert fd == pytest.approx(F[atom, ax], rel=1e-4, abs=1e-6)
+    api.ased_build(ctx, pair, s, scale)
+
+
+def test_water3000_sampled_residuals_mixed_and_fp64():
+    """Water box at full size (3000 H2O, N = 18000, B = 6, 1024 shifts):
+    complex64 forward (tol 1e-6) and FP64 forward on sampled right-hand
+    sides; true residuals of sampled (shift, rhs) pairs with the oracle's own
+    sparse S and H.  Complex64 products bound the attainable residual by
+    about kappa * eps32, so the mixed bound is looser than its recursion
+    tolerance."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1002_1202_amd import api
+    cfg = configs.water3000()
+    s, z = cfg["system"], cfg["z"]
+    rng = np.random.default_rng(1)
+    rhs = np.sort(rng.choice(s.n, 32, replace=False)).astype(np.int64)
+    print(f"case: water3000 full size N={s.n} K={len(z)} R={len(rhs)}", flush=True)
+    ctx = api.Context(0)
+    pair, scale = api.pair_from_system(ctx, s)
+    Sb, Hb, c0 = oased.pair_blocks(s)
+    assert abs(scale - c0) <= 1e-13 * c0
+    S, H = ogreen.sparse_matrices(s, Sb, Hb)
+    ks = rng.choice(len(z), 6, replace=False)
+    worst = {}
+    G = {}
+    for prec, tol in (("mixed", 1e-6), ("fp64", 1e-10)):
+        res = api.solve(ctx, pair, z, rhs=rhs, out="device", tol=tol, precision=prec)
+        assert res.converged.all()
+        wr = 0.0
+        for k in ks:
+            for r in range(0, len(rhs), 5):
+                x = res.G_cols[k, r].cpu().numpy()
+                b = np.zeros(s.n, complex)
+                b[rhs[r]] = 1.0
+                wr = max(wr, np.linalg.norm(b - (z[k] * (S @ x) - H @ x)))
+        worst[prec] = wr
+        G[prec] = res.G_cols[ks].cpu().numpy()
+        del res
+    err = float(np.abs(G["mixed"] - G["fp64"]).max() / np.abs(G["fp64"]).max())
+    print(f"  true residual mixed {worst['mixed']:.2e} fp64 {worst['fp64']:.2e}; |G_mixed - G_fp64| / max|G| "
+          f"= {err:.2e}", flush=True)
+    assert worst["fp64"] < 1e-8
+    assert worst["mixed"] < 1e-3
+    assert err < 1e-3
