@@ -1,10 +1,14 @@
-"""torch.autograd glue for the band energy and the ASED pair.
+"""torch.autograd glue for the band energy, the Mulliken charges and the
+ASED pair.
 
 ``BandEnergy`` runs one shifted solve with the z-derivative carry in its
 forward (E_band together with dE/dH and dE/dS, the backward reusing the same
 shifted solver); its backward only scales the stored gradients by the
-incoming scalar.  ``AsedPair`` builds S, H on the device from positions and
-maps (dE/dH, dE/dS) to dE/dpos with the library's VJP kernels.
+incoming scalar.  ``MullikenCharges`` returns the charges of listed orbitals;
+its backward solves for G e_a and G S e_a and contracts them with the
+incoming charge gradient on the pattern (the general charge-loss adjoint).
+``AsedPair`` builds S, H on the device from positions and maps (dE/dH,
+dE/dS) to dE/dpos with the library's VJP kernels.
 """
 from __future__ import annotations
 
@@ -31,6 +35,26 @@ class BandEnergy(torch.autograd.Function):
         return gE * dH, gE * dS, None, None, None, None, None
 
 
+class MullikenCharges(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, Hval, Sval, gctx, pair, z, w, orbs, opts):
+        pair.set_values(Hval.detach().contiguous(), Sval.detach().contiguous())
+        q, _, _, info = api.mulliken_band(gctx, pair, z, w, orbs, **opts)
+        fctx.gctx, fctx.pair, fctx.z, fctx.w, fctx.orbs, fctx.opts = gctx, pair, z, w, orbs, opts
+        fctx.info = info
+        return torch.from_numpy(q).to(Hval.device)
+
+    @staticmethod
+    def backward(fctx, gq):
+        qbar = gq.detach().cpu().numpy().astype(np.float64)
+        shape = (fctx.pair.nnzb, fctx.pair.block, fctx.pair.block)
+        dH = torch.zeros(shape, dtype=torch.float64, device=gq.device)
+        dS = torch.zeros_like(dH)
+        opts = {k: v for k, v in fctx.opts.items() if k != "carry"}
+        api.charge_vjp(fctx.gctx, fctx.pair, fctx.z, fctx.w, fctx.orbs, qbar, dH=dH, dS=dS, **opts)
+        return dH, dS, None, None, None, None, None, None
+
+
 class AsedPair(torch.autograd.Function):
     @staticmethod
     def forward(fctx, pos, gctx, pair, system, scale):
@@ -47,6 +71,13 @@ class AsedPair(torch.autograd.Function):
                          positions=fctx.p)
         g = torch.from_numpy(-F).to(fctx.pos_device)
         return g, None, None, None, None
+
+
+def mulliken_charges(gctx, pair, system, pos, z, w, orbs, scale, **opts):
+    """Mulliken charges q_a(pos) of the orbitals ``orbs`` with autograd
+    through the ASED pair (scale c held fixed)."""
+    H, S = AsedPair.apply(pos, gctx, pair, system, scale)
+    return MullikenCharges.apply(H, S, gctx, pair, z, w, np.asarray(orbs, dtype=np.int64), opts)
 
 
 def band_energy(gctx, pair, system, pos, z, w, scale, **opts):

@@ -65,3 +65,39 @@ def test_charge_vjp_band_energy_consistency(ctx):
     dH, dS, _ = api.charge_vjp(ctx, pair, z, w * z.real, np.arange(s.n), np.ones(s.n), tol=1e-12)
     eH, eS, _, _ = api.band_energy_vjp(ctx, pair, z, w, tol=1e-12)
     assert rel(dH, eH) < 1e-9 and rel(dS, eS) < 1e-9
+
+
+def test_autograd_charge_loss_forces(ctx):
+    """A loss of the charges through autograd (charges -> pair -> positions)
+    against the dense oracle's gradient chained by the oracle's forces, and
+    against central differences of the same loss."""
+    import torch
+    from paper_1002_1202_amd import api, autograd
+    c = configs.water_small(n_mol=6, n_rhs=4, n_shift=12, eta=0.3)
+    s, z = c["system"], c["z"]
+    print("case: autograd charge loss forces", flush=True)
+    w = np.full(len(z), 0.4)
+    orbs = np.array([0, 5, 13, 20, 31])
+    cvec = np.array([1.0, -0.5, 2.0, 0.3, -1.2])
+    pair, scale = api.pair_from_system(ctx, s)
+    pos = torch.tensor(s.positions, dtype=torch.float64, requires_grad=True)
+    q = autograd.mulliken_charges(ctx, pair, s, pos, z, w, orbs, scale, tol=1e-12)
+    loss = (q * torch.from_numpy(cvec).to(q.device)).sum()
+    loss.backward()
+    F = -pos.grad.numpy()
+    S, H, _ = oased.dense_pair(s, c=scale)
+    gH, gS = ogreen.charge_grad_dense(H, S, z, w, orbs, cvec)
+    F0 = oased.forces(s, oased.gather_blocks(s, gH), oased.gather_blocks(s, gS), scale)
+    print(f"  |F - F0| / |F0| = {rel(F, F0):.2e}", flush=True)
+    assert rel(F, F0) < 1e-8
+    h = 1e-4
+    for atom, ax in [(0, 0), (4, 2)]:
+        vals = []
+        for sgn in (1, -1):
+            p = s.positions.copy()
+            p[atom, ax] += sgn * h
+            api.ased_build(ctx, pair, s, scale, positions=p)
+            qq, _, _, _ = api.mulliken_band(ctx, pair, z, w, orbs, tol=1e-13)
+            vals.append(float(cvec @ qq))
+        fd = -(vals[0] - vals[1]) / (2 * h)
+        assert fd == pytest.approx(F[atom, ax], rel=1e-5, abs=1e-7)
