@@ -155,15 +155,6 @@ __device__ inline double cheb_update(cpx<T> own, cpx<T> Sx, const cpx<T> *__rest
 
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
-// Algorithmic-byte counter of a launch (profiling only; ctr may be null):
-// each wave adds (active lanes) x per_lane bytes.
-__device__ inline void count_bytes(unsigned long long *ctr, bool active, unsigned long long per_lane) {
-    if (ctr == nullptr) return;
-    const unsigned long long mask = __ballot(active);
-    if ((threadIdx.x & 63) == 0 && mask != 0ull)
-        atomicAdd(ctr, static_cast<unsigned long long>(__popcll(mask)) * per_lane);
-}
-
 // rows handled by wave w of a row group [i0, i1) (waves interleave rows)
 __device__ inline int wave_rows(int i0, int i1, int w) {
     const int n = i1 - i0 - w;

@@ -591,7 +591,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_update(int N, int Rp, int Lr, const int *inner_done,
                                                       const int *first, const double *cg_a,
                                                       const cpx<T> *d, const cpx<T> *w, cpx<T> *y,
-                                                      cpx<T> *res, double *partial, unsigned long long *ctr) {
+                                                      cpx<T> *res, double *partial) {
     ELEM_LOOP_BEGIN
     double acc = 0.0;
     if (!inner_done[col]) {
@@ -612,8 +612,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int N, int Rp, int Lr, con
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_dir(int N, int Rp, int Lr, const int *inner_done,
-                                                   const double *cg_b, const cpx<T> *res, cpx<T> *d,
-                                                   unsigned long long *ctr) {
+                                                   const double *cg_b, const cpx<T> *res, cpx<T> *d) {
     ELEM_LOOP_BEGIN
     if (inner_done[col]) return;
     const T b = static_cast<T>(cg_b[col]);
@@ -626,8 +625,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(int N, int Rp, int Lr, const 
 // partial r'^T r (unconjugated)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rho_dot(int N, int Rp, int Lr, const int *done, const int *zres,
-                                                    const cpx<T> *rp, const cpx<T> *r, c128 *partial,
-                                                    unsigned long long *ctr) {
+                                                    const cpx<T> *rp, const cpx<T> *r, c128 *partial) {
     ELEM_LOOP_BEGIN
     c128 acc{0, 0};
     if (!done[col] && !zres[col]) {
@@ -1471,7 +1469,7 @@ template <typename T> class TileSolver {
         }
         if (o.inner_method != 1) setup_chebyshev(o, inner_tol);
         k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), t_.ring.get(),
-                                        t_.r.get(), t_.part_c.get(), nullptr);
+                                        t_.r.get(), t_.part_c.get());
         k_init_rho<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_c.get(), cs);
         k_p_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, 1, cs, t_.ring.get(), t_.r.get(), t_.p.get(),
                                          t_.P.get(), t_.ldk, nullptr);
@@ -1499,7 +1497,7 @@ template <typename T> class TileSolver {
         k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 0, inner_tol_, cs);
         inner_solve_cheb(o, cs, rp);
         k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), rp, t_.r.get(),
-                                        t_.part_c.get(), nullptr);
+                                        t_.part_c.get());
         k_post<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.G, n, 0, t_.part_c.get(), o.tol, cs, ss, t_.h.get(),
                                           t_.dh.get(), t_.Mu + t_.srow);
         k_p_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, 0, cs, rp, t_.r.get(), t_.p.get(), t_.P.get(),
@@ -1540,7 +1538,7 @@ template <typename T> class TileSolver {
             cpx<T> *rp_next = t_.ring.get() + slot_next * NR;
             prof_.begin(st_, KP_SPMM_SEED, 2.0 * mat_bytes());
             launch_spmm_seed<T>(st_, pr_, td, Sv, Hv, t_.p.get(), t_.q.get(), dz_, t_.c_seed.get(),
-                                t_.c_done.get(), t_.part_c.get(), ctr(KP_SPMM_SEED));
+                                t_.c_done.get(), t_.part_c.get());
             prof_.end(st_);
             prof_.begin(st_, KP_CTRL, 0.0);
             k_ctrl<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.Gs, n, slot, t_.part_c.get(), cs, ss);
@@ -1562,7 +1560,7 @@ template <typename T> class TileSolver {
             inner_solve(o, cs, rp_next);
             prof_.begin(st_, KP_RHO_DOT, 0.0);
             k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), rp_next,
-                                            t_.r.get(), t_.part_c.get(), ctr(KP_RHO_DOT));
+                                            t_.r.get(), t_.part_c.get());
             prof_.end(st_);
             prof_.begin(st_, KP_POST, 0.0);
             k_post<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.G, n, full_ ? 1 : 0, t_.part_c.get(), o.tol, cs,
@@ -1786,7 +1784,6 @@ template <typename T> class TileSolver {
   private:
     const T *sval() const;
     const T *hval() const;
-    unsigned long long *ctr(int) { return nullptr; }
 
     // Algorithmic bytes of every kernel class over this solve (the method's
     // own reads and writes of N-long vectors; gathers and re-reads excluded),
@@ -1942,19 +1939,18 @@ template <typename T> class TileSolver {
         while (true) {
             for (int j = 0; j < chunk; ++j) {
                 prof_.begin(st_, KP_SPMM_S, mat_bytes() + 2 * vec);
-                launch_spmm_S<T>(st_, pr_, td, Sv, t_.d.get(), t_.w.get(), t_.c_inner_done.get(), t_.part_d.get(),
-                                 ctr(KP_SPMM_S));
+                launch_spmm_S<T>(st_, pr_, td, Sv, t_.d.get(), t_.w.get(), t_.c_inner_done.get(), t_.part_d.get());
                 prof_.end(st_);
                 k_cg_a<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), cs);
                 prof_.begin(st_, KP_CG_UPDATE, 6 * vec);
                 k_cg_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_inner_done.get(), t_.c_cg_first.get(),
                                                   t_.c_cg_a.get(), t_.d.get(), t_.w.get(), y, t_.res.get(),
-                                                  t_.part_d.get(), ctr(KP_CG_UPDATE));
+                                                  t_.part_d.get());
                 prof_.end(st_);
                 k_cg_b<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), o.inner_max_iter, cs);
                 prof_.begin(st_, KP_CG_DIR, 3 * vec);
                 k_cg_dir<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_inner_done.get(), t_.c_cg_b.get(),
-                                               t_.res.get(), t_.d.get(), ctr(KP_CG_DIR));
+                                               t_.res.get(), t_.d.get());
                 prof_.end(st_);
             }
             GSC_HIP(hipGetLastError());

@@ -11,11 +11,11 @@ void set_spmm_geometry(TileDims &td, const Pair &pr, int variant);
 template <typename T>
 void launch_spmm_seed(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const T *Hv,
                       const cpx<T> *p, cpx<T> *q, const c128 *z, const int *seed, const int *skip,
-                      c128 *partial, unsigned long long *ctr = nullptr);
+                      c128 *partial);
 
 template <typename T>
 void launch_spmm_S(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const cpx<T> *d,
-                   cpx<T> *w, const int *skip, double *partial, unsigned long long *ctr = nullptr);
+                   cpx<T> *w, const int *skip, double *partial);
 
 template <typename T>
 void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, int mode, const T *Sv,

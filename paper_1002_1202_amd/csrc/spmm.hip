@@ -20,7 +20,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_seed(
     int nb, int Rp, int Lb, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const T *__restrict__ Sv, const T *__restrict__ Hv, const cpx<T> *__restrict__ p,
     cpx<T> *__restrict__ q, const c128 *__restrict__ z, const int *__restrict__ seed,
-    const int *__restrict__ skip, c128 *__restrict__ partial, unsigned long long *ctr) {
+    const int *__restrict__ skip, c128 *__restrict__ partial) {
     int cx, g;
     xcd_remap_chunks(cx, g);
     const int lane = threadIdx.x & 63;
@@ -90,7 +90,7 @@ template <typename T, int B>
 __global__ __launch_bounds__(kBlock) void k_spmm_S(
     int nb, int Rp, int Lb, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const T *__restrict__ Sv, const cpx<T> *__restrict__ d, cpx<T> *__restrict__ wout,
-    const int *__restrict__ skip, double *__restrict__ partial, unsigned long long *ctr) {
+    const int *__restrict__ skip, double *__restrict__ partial) {
     int cx, g;
     xcd_remap_chunks(cx, g);
     const int lane = threadIdx.x & 63;
@@ -441,7 +441,7 @@ inline void cluster_geometry(const Pair &pr, const TileDims &td, int &gy, int &L
 template <typename T>
 void launch_spmm_seed(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const T *Hv,
                       const cpx<T> *p, cpx<T> *q, const c128 *z, const int *seed, const int *skip,
-                      c128 *partial, unsigned long long *ctr) {
+                      c128 *partial) {
     dim3 grid(td.Rp / 64, td.Gs), block(kBlock);
     if (td.variant == 2) {
         launch_spmm_seed_slab<T>(st, pr, td, Sv, Hv, p, q, z, seed, skip, partial);
@@ -463,16 +463,16 @@ void launch_spmm_seed(hipStream_t st, const Pair &pr, const TileDims &td, const 
     }
     if (pr.B == 4)
         k_spmm_seed<T, 4><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(),
-                                                  Sv, Hv, p, q, z, seed, skip, partial, ctr);
+                                                  Sv, Hv, p, q, z, seed, skip, partial);
     else
         k_spmm_seed<T, 6><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(),
-                                                  Sv, Hv, p, q, z, seed, skip, partial, ctr);
+                                                  Sv, Hv, p, q, z, seed, skip, partial);
     GSC_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_spmm_S(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const cpx<T> *d,
-                   cpx<T> *w, const int *skip, double *partial, unsigned long long *ctr) {
+                   cpx<T> *w, const int *skip, double *partial) {
     dim3 grid(td.Rp / 64, td.Gs), block(kBlock);
     if (td.variant == 2) {
         launch_spmm_S_slab<T>(st, pr, td, Sv, d, w, skip, partial);
@@ -492,22 +492,22 @@ void launch_spmm_S(hipStream_t st, const Pair &pr, const TileDims &td, const T *
     }
     if (pr.B == 4)
         k_spmm_S<T, 4><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(), Sv,
-                                               d, w, skip, partial, ctr);
+                                               d, w, skip, partial);
     else
         k_spmm_S<T, 6><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(), Sv,
-                                               d, w, skip, partial, ctr);
+                                               d, w, skip, partial);
     GSC_HIP(hipGetLastError());
 }
 
 template void launch_spmm_seed<double>(hipStream_t, const Pair &, const TileDims &, const double *,
                                        const double *, const c128 *, c128 *, const c128 *, const int *,
-                                       const int *, c128 *, unsigned long long *);
+                                       const int *, c128 *);
 template void launch_spmm_seed<float>(hipStream_t, const Pair &, const TileDims &, const float *,
                                       const float *, const c64 *, c64 *, const c128 *, const int *,
-                                      const int *, c128 *, unsigned long long *);
+                                      const int *, c128 *);
 template void launch_spmm_S<double>(hipStream_t, const Pair &, const TileDims &, const double *,
-                                    const c128 *, c128 *, const int *, double *, unsigned long long *);
+                                    const c128 *, c128 *, const int *, double *);
 template void launch_spmm_S<float>(hipStream_t, const Pair &, const TileDims &, const float *, const c64 *,
-                                   c64 *, const int *, double *, unsigned long long *);
+                                   c64 *, const int *, double *);
 
 }  // namespace gsc
