@@ -1,0 +1,122 @@
+"""Degenerate and edge cases of the HIP path, checked against closed forms
+that do not go through the oracle: an identity overlap with a diagonal
+Hamiltonian (G_jj = 1 / (z - eps_j), the seed converging in one step, the
+Lanczos process exhausting its Krylov space at once), a two-block system
+inverted in closed form (one shift, one right-hand side), and right-hand-side
+counts at the 64-column tile boundary."""
+import numpy as np
+import pytest
+
+from oracle import ased as oased, green as ogreen
+from synth import configs
+from synth.grids import shift_grid, trapezoid_weights
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1002_1202_amd import api
+    return api.Context(0)
+
+
+def diagonal_pair(ctx, nat, B, seed):
+    from paper_1002_1202_amd import api
+    rng = np.random.default_rng(seed)
+    eps = rng.uniform(-15.0, -5.0, size=nat * B)
+    H = np.zeros((nat, B, B))
+    S = np.zeros((nat, B, B))
+    for a in range(nat):
+        H[a] = np.diag(eps[a * B:(a + 1) * B])
+        S[a] = np.eye(B)
+    pair = api.Pair(ctx, B, np.arange(nat + 1), np.arange(nat, dtype=np.int32), H, S)
+    return pair, eps
+
+
+@pytest.mark.parametrize("B,inner,prec", [(4, 2, "fp64"), (4, 1, "fp64"), (6, 2, "fp64"), (4, 2, "mixed")])
+def test_identity_overlap_diagonal_closed_form(ctx, B, inner, prec):
+    from paper_1002_1202_amd import api
+    print(f"case: S = I, diagonal H, B={B} inner={inner} {prec}", flush=True)
+    nat = 5
+    pair, eps = diagonal_pair(ctx, nat, B, seed=B)
+    n = nat * B
+    z = shift_grid(-20.0, 0.0, 9, 0.1)
+    rhs = np.arange(n)
+    g = 1.0 / (z[:, None] - eps[None, :])                     # [K][n]
+    tol_g = 1e-12 if prec == "fp64" else 1e-5
+    res = api.solve(ctx, pair, z, rhs=rhs, tol=1e-13 if prec == "fp64" else 1e-6, inner_method=inner,
+                    precision=prec)
+    assert res.status == 0 and res.converged.all()
+    ref = np.zeros((len(z), n, n), dtype=complex)
+    ref[:, np.arange(n), np.arange(n)] = g
+    print(f"  iters={res.outer_iters} err={rel(res.G_cols, ref):.2e}", flush=True)
+    assert res.outer_iters <= 2
+    assert rel(res.G_cols, ref) < tol_g
+    resp = api.solve(ctx, pair, z, rhs=rhs, tol=1e-13 if prec == "fp64" else 1e-6, inner_method=inner,
+                     precision=prec, carry="projected", proj=rhs[:, None])
+    assert rel(resp.G_proj[:, :, 0], g) < tol_g
+    w = trapezoid_weights(z)
+    q, e, eb, _ = api.mulliken_band(ctx, pair, z, w, rhs, tol=1e-13 if prec == "fp64" else 1e-6,
+                                    inner_method=inner, precision=prec)
+    q0 = -(2.0 / np.pi) * (w[:, None] * g.imag).sum(0)
+    e0 = -(2.0 / np.pi) * ((w * z.real)[:, None] * g.imag).sum(0)
+    assert np.abs(q - q0).max() < tol_g * np.abs(q0).max()
+    assert np.abs(e - e0).max() < tol_g * np.abs(e0).max()
+    assert abs(eb - e0.sum()) < tol_g * np.abs(e0).sum()
+    lz = api.lanczos_green(ctx, pair, z, rhs, m_max=8, tol=1e-13 if prec == "fp64" else 1e-6,
+                           check_every=1, precision=prec)
+    print(f"  lanczos steps {lz.steps.min()}..{lz.steps.max()} err={rel(lz.G_diag, g):.2e}", flush=True)
+    assert lz.steps.max() <= (1 if prec == "fp64" else 4)
+    assert rel(lz.G_diag, g) < tol_g
+
+
+def test_two_blocks_one_shift_one_rhs_closed_form(ctx):
+    """Two 4x4 block rows, full 2x2 block pattern, S = [[I, C], [C^T, I]];
+    one shift and one right-hand side, against the 8x8 inverse."""
+    from paper_1002_1202_amd import api
+    print("case: two blocks, K=1, R=1", flush=True)
+    rng = np.random.default_rng(3)
+    B = 4
+    C = 0.15 * rng.uniform(-1.0, 1.0, size=(B, B))
+    Hd = [np.diag(rng.uniform(-14.0, -6.0, size=B)) for _ in range(2)]
+    Ho = 1.75 * 0.5 * (-10.0) * C
+    S = np.stack([np.eye(B), C, C.T, np.eye(B)])
+    H = np.stack([Hd[0], Ho, Ho.T, Hd[1]])
+    pair = api.Pair(ctx, B, np.array([0, 2, 4]), np.array([0, 1, 0, 1], dtype=np.int32), H, S)
+    Sd = np.block([[S[0], S[1]], [S[2], S[3]]])
+    Hdn = np.block([[H[0], H[1]], [H[2], H[3]]])
+    z = np.array([-9.3 + 0.07j])
+    j = 5
+    inv = np.linalg.inv(z[0] * Sd - Hdn)
+    for inner in (1, 2):
+        res = api.solve(ctx, pair, z, rhs=np.array([j]), tol=1e-13, inner_method=inner)
+        print(f"  inner={inner} iters={res.outer_iters} err={rel(res.G_cols[0, 0], inv[:, j]):.2e}", flush=True)
+        assert res.status == 0
+        assert rel(res.G_cols[0, 0], inv[:, j]) < 1e-11
+        lz = api.lanczos_green(ctx, pair, z, np.array([j]), m_max=16, tol=1e-13, check_every=1,
+                               inner_method=inner)
+        assert abs(lz.G_diag[0, 0] - inv[j, j]) < 1e-11 * abs(inv[j, j])
+
+
+@pytest.mark.parametrize("nrhs", [1, 63, 64, 65, 128])
+def test_rhs_counts_at_tile_boundaries(ctx, nrhs):
+    from paper_1002_1202_amd import api
+    print(f"case: si64 nrhs={nrhs}", flush=True)
+    c = configs.si_small(cells=(2, 2, 2), n_shift=6, eta=0.2, seed=5)
+    s = c["system"]
+    S, H, _ = oased.dense_pair(s)
+    pair, _ = api.pair_from_system(ctx, s)
+    rhs = np.random.default_rng(nrhs).choice(s.n, size=nrhs, replace=False)
+    X = ogreen.solve_dense(H, S, c["z"], rhs)
+    res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12)
+    assert res.converged.all()
+    assert rel(res.G_cols, X) < 1e-10
+    resp = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, carry="projected", proj=rhs[:, None])
+    assert rel(resp.G_proj[:, :, 0], X[:, np.arange(nrhs), rhs]) < 1e-10
