@@ -82,6 +82,29 @@ def cpu_baseline(cfg, iters):
                       f"steps) in {dt:.1f} s"}
 
 
+def cpu_dense_lu(cfg, n_shifts=1):
+    """The plain definition of the result, timed the way a dense solver would
+    run it: dense z S - H and LAPACK LU (oracle/green.py) for every right-hand
+    side of the workload at ``n_shifts`` shifts, on all BLAS threads of the
+    host; reported per shift and extrapolated to all shifts."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import ased, green
+
+    s = cfg["system"]
+    S, H, _ = ased.dense_pair(s)
+    z = cfg["z"][:n_shifts]
+    t0 = time.perf_counter()
+    green.solve_dense(H, S, z, cfg["rhs"])
+    dt = (time.perf_counter() - t0) / n_shifts
+    threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
+    return {"kind": "oracle dense LU (numpy/scipy LAPACK)", "threads": threads,
+            "seconds_per_shift": dt, "extrapolated_seconds_all_shifts": dt * len(cfg["z"]),
+            "sample": f"{n_shifts} shift(s) x {len(cfg['rhs'])} rhs of {cfg['name']} (N={s.n}, dense "
+                      f"{s.n}x{s.n} complex LU per shift)"}
+
+
 def copy_bandwidth(reps=10):
     """Measured device-to-device copy rate (GB/s, bytes read + written) of a
     1 GiB FP64 tensor, best of ``reps`` launches timed with events on torch's
@@ -275,13 +298,15 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=60)
+    ap.add_argument("--cpu-iters", type=int, default=300)
     ap.add_argument("--spmm", type=int, default=0,
                     help="0 auto, 1 row kernel, 2 cluster, 3 slab, 4 split-orbital Chebyshev")
     ap.add_argument("--inner", type=int, default=0, help="0 auto, 1 CG, 2 Chebyshev")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate launch shapes on this problem first and use the fastest")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-dense-lu", action="store_true",
+                    help="skip timing the dense-LU oracle on the host (one shift, all BLAS threads)")
     ap.add_argument("--no-lanczos", action="store_true")
     ap.add_argument("--no-scc", action="store_true")
     ap.add_argument("--no-charge-vjp", action="store_true")
@@ -425,6 +450,10 @@ def main():
         line["batched"] = batched_compare(ctx)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters)
+        print(f"cpu baseline: {line['cpu_baseline']['sample']}", file=sys.stderr, flush=True)
+        if not args.no_dense_lu:
+            line["cpu_dense_lu"] = cpu_dense_lu(cfg)
+            print(f"cpu dense LU: {line['cpu_dense_lu']}", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

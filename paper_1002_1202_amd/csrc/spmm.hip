@@ -34,9 +34,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_seed(
     const int I1 = min(nb, I0 + Lb);
     if (__ballot(act) != 0) {
         for (int I = I0 + w; I < I1; I += kWavesPerBlock) {
-            cpx<T> aS[B], aH[B], own[B];
+            cpx<T> aS[B], aH[B];
 #pragma unroll
-            for (int a = 0; a < B; ++a) { aS[a] = {0, 0}; aH[a] = {0, 0}; own[a] = {0, 0}; }
+            for (int a = 0; a < B; ++a) { aS[a] = {0, 0}; aH[a] = {0, 0}; }
             const int b0 = rowptr[I], b1 = rowptr[I + 1];
 #pragma unroll 2
             for (int b = b0; b < b1; ++b) {
@@ -47,10 +47,6 @@ __global__ __launch_bounds__(kBlock) void k_spmm_seed(
 #pragma unroll
                 for (int c = 0; c < B; ++c)
                     x[c] = act ? p[static_cast<size_t>(J * B + c) * Rp + col] : cpx<T>{0, 0};
-                if (J == I) {
-#pragma unroll
-                    for (int c = 0; c < B; ++c) own[c] = x[c];
-                }
 #pragma unroll
                 for (int a = 0; a < B; ++a) {
 #pragma unroll
@@ -63,12 +59,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm_seed(
                     }
                 }
             }
+            // the row's own p values (diagonal block) are re-read: an L2 hit,
+            // cheaper than holding them in registers through the row
 #pragma unroll
             for (int a = 0; a < B; ++a) {
                 const cpx<T> v = zt * aS[a] - aH[a];
                 if (act) {
-                    q[static_cast<size_t>(I * B + a) * Rp + col] = v;
-                    dot = dot + ccast<double>(own[a]) * ccast<double>(v);
+                    const size_t e = static_cast<size_t>(I * B + a) * Rp + col;
+                    q[e] = v;
+                    dot = dot + ccast<double>(p[e]) * ccast<double>(v);
                 }
             }
         }
