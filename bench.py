@@ -105,6 +105,75 @@ def cpu_dense_lu(cfg, n_shifts=1):
                       f"{s.n}x{s.n} complex LU per shift)"}
 
 
+def forces_measure(name, n_slices=8, precision=None):
+    """One MD-style step at full size: the band energy over every orbital,
+    its gradients on the stored H, S entries (one shifted solve with the
+    z-derivative carry) and the forces through the ASED pair.  slab8192: FP64,
+    tol 1e-10, 512 shifts on [-20, E_F]; water3000: complex64 products, FP64
+    recurrences, tol 1e-6, 1024 shifts on [-40, 5] eV weighted up to the
+    mid-gap Fermi level of a small box of the same model."""
+    import numpy as np
+    import torch
+
+    from paper_1002_1202_amd import api
+    from synth import configs
+    from synth.grids import trapezoid_weights
+
+    if name == "slab8192":
+        cfg = configs.slab8192()
+        w, ef = cfg["w"], cfg["e_fermi"]
+    elif name == "water3000":
+        from oracle import ased as oased, spectral as ospec
+        cfg = configs.water3000()
+        small = configs.water_small(n_mol=8, n_rhs=4)["system"]
+        S, H0, _ = oased.dense_pair(small)
+        ev, _ = ospec.eig_pencil(H0, S)
+        nocc = int(round(small.valence.sum() / 2))
+        ef = float(0.5 * (ev[nocc - 1] + ev[nocc]))
+        w = trapezoid_weights(cfg["z"]) * (cfg["z"].real <= ef)
+    else:
+        raise SystemExit(f"unknown forces workload {name}")
+    if precision is not None:
+        cfg["precision"] = precision
+    s, z = cfg["system"], cfg["z"]
+    ctx = api.Context(0)
+    pair, scale = api.pair_from_system(ctx, s)
+    shape = (pair.nnzb, pair.block, pair.block)
+    dH = torch.zeros(shape, dtype=torch.float64, device="cuda:0")
+    dS = torch.zeros_like(dH)
+    print(f"forces {name}: N={s.n} K={len(z)} precision={cfg['precision']} tol={cfg['tol']}",
+          file=sys.stderr, flush=True)
+    # the gradient's columns split over slices of orbitals (each slice one
+    # call; the slices add up to the full band energy and its gradient)
+    slices = np.array_split(np.arange(s.n, dtype=np.int64), n_slices)
+    E, iters, inner, work, conv = 0.0, 0, 0, 0, []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, orbs in enumerate(slices):
+        _, _, e, info = api.band_energy_vjp(ctx, pair, z, w, 1.0, dH, dS, orbs=orbs, tol=cfg["tol"],
+                                            precision=cfg["precision"])
+        E += e
+        iters = max(iters, info["outer_iters"])
+        inner += info["inner_iters"]
+        work += info["shift_rhs_iters"]
+        conv.append(info["converged"])
+        print(f"forces {name}: slice {i + 1}/{len(slices)} ({len(orbs)} orbitals) done at "
+              f"{time.perf_counter() - t0:.1f} s, {info['outer_iters']} outer iterations", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    F = api.ased_vjp(ctx, pair, s, scale, dH, dS)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"metric": "band energy + forces, all orbitals", "workload": name,
+            "system": f"{s.n_atoms} atoms, N={s.n}, nnzb={s.nnzb}, block={s.block}", "shifts": int(len(z)),
+            "rhs": int(s.n), "slices": len(slices), "precision": cfg["precision"], "tol": cfg["tol"],
+            "e_fermi": ef, "seconds_solve_with_gradients": t1 - t0, "seconds_forces_from_gradients": t2 - t1,
+            "outer_iters": iters, "inner_iters": inner, "shift_rhs_iters": work,
+            "value": work / (t1 - t0), "unit": UNIT,
+            "converged_frac": float(np.mean(np.concatenate([c.ravel() for c in conv]))), "E_band": E,
+            "max_abs_force": float(np.abs(F).max()), "abs_sum_force": float(np.abs(F.sum(0)).max())}
+
+
 def copy_bandwidth(reps=10):
     """Measured device-to-device copy rate (GB/s, bytes read + written) of a
     1 GiB FP64 tensor, best of ``reps`` launches timed with events on torch's
@@ -304,6 +373,11 @@ def main():
     ap.add_argument("--inner", type=int, default=0, help="0 auto, 1 CG, 2 Chebyshev")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate launch shapes on this problem first and use the fastest")
+    ap.add_argument("--forces", default=None, choices=["slab8192", "water3000"],
+                    help="instead of the throughput line: one band energy + forces step over every "
+                         "orbital of a full-size workload (its own JSON line)")
+    ap.add_argument("--forces-precision", default=None, choices=["fp64", "mixed"],
+                    help="override the forces workload's precision (slab8192: fp64, water3000: mixed)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-dense-lu", action="store_true",
                     help="skip timing the dense-LU oracle on the host (one shift, all BLAS threads)")
@@ -331,6 +405,9 @@ def main():
         torch.cuda.synchronize()
         print(f"copy probe: {a.numel() * 8} bytes read and written", file=sys.stderr, flush=True)
         del a, b
+    if args.forces:
+        print(json.dumps(forces_measure(args.forces, precision=args.forces_precision)), flush=True)
+        return
     cfg = workload(args.workload)
     if args.tol is None:
         args.tol = cfg["tol"]

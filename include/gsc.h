@@ -311,17 +311,24 @@ gsc_status gsc_mulliken_band(gsc_ctx *ctx, const gsc_pair *pair, int nshift, con
                              const gsc_opts *opts, double *q_orb, double *e_orb,
                              double *e_band, int out_mem, gsc_stats *stats);
 
-/* Backward of the full band energy E = sum_a e_a over ALL orbitals:
+/* Backward of the band energy E = sum_a e_a over all orbitals (Sec. 2.2 with
+ * the gradient of the Green's function, dG = G dH G, dG = -z G dS G):
  *   dH += grad_E * dE/dH_bc = -(2/pi) sum_k w_k E_k Im[(G_k S G_k)_bc]
  *   dS += grad_E * dE/dS_bc = -(2/pi) sum_k w_k E_k Im[(G_k - z_k G_k S G_k)_bc]
  * on the stored entries (block layout of the pair values, per `mem`).
- * G S G b = -dx(z)/dz is carried alongside the shifted iterates, so the
- * backward reuses the same shifted solver.  *e_band (HOST, may be NULL)
- * receives the band energy of the same solve. */
+ * Column c of both gradients comes from the solve with right-hand side e_c
+ * alone: G S G e_c = -dx(z)/dz is carried alongside the shifted iterates, so
+ * the backward reuses the same shifted solver.  The call covers the columns
+ * c = orb_idx[0 .. norb-1] (HOST, distinct, in range; orb_idx == NULL with
+ * norb == N: every orbital): it adds those columns of the full gradient and
+ * writes *e_band (HOST, may be NULL) = sum over the listed c of e_c.  Calls
+ * over a partition of the orbitals therefore add up to the gradient and the
+ * value of the full band energy (a caller can split a large system into
+ * slices).  GSC_E_ARG for a repeated or out-of-range orbital. */
 gsc_status gsc_band_energy_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const double *z,
-                               const double *w, double grad_E, const gsc_opts *opts,
-                               double *dHval, double *dSval, double *e_band, int mem,
-                               gsc_stats *stats);
+                               const double *w, int norb, const int64_t *orb_idx, double grad_E,
+                               const gsc_opts *opts, double *dHval, double *dSval, double *e_band,
+                               int mem, gsc_stats *stats);
 
 /* ---- kernel timing ------------------------------------------------------- */
 /* Live per-kernel timing with HIP events recorded on the context's stream

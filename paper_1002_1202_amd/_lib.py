@@ -73,8 +73,8 @@ SIGNATURES = {
                             C.c_int, _I64P, _VP, C.c_int, C.POINTER(Stats)]),
     "gsc_mulliken_band": (C.c_int, [_VP, _VP, C.c_int, _DP, _DP, C.c_int, _I64P, C.POINTER(Opts),
                                     _VP, _VP, _DP, C.c_int, C.POINTER(Stats)]),
-    "gsc_band_energy_vjp": (C.c_int, [_VP, _VP, C.c_int, _DP, _DP, C.c_double, C.POINTER(Opts),
-                                      _VP, _VP, _DP, C.c_int, C.POINTER(Stats)]),
+    "gsc_band_energy_vjp": (C.c_int, [_VP, _VP, C.c_int, _DP, _DP, C.c_int, _I64P, C.c_double,
+                                      C.POINTER(Opts), _VP, _VP, _DP, C.c_int, C.POINTER(Stats)]),
     "gsc_solve_batched": (C.c_int, [_VP, C.c_int, C.POINTER(Problem), C.POINTER(Opts)]),
     "gsc_charge_vjp": (C.c_int, [_VP, _VP, C.c_int, _DP, _DP, C.c_int, _I64P, _DP, C.POINTER(Opts), _VP, _VP,
                                  C.c_int, C.POINTER(Stats)]),

@@ -440,14 +440,22 @@ def lanczos_green(ctx: Context, pair: Pair, z, rhs, m_max: int = 2000, tol: floa
     return LanczosResult(G, a, b, steps, status, st.outer_iters, st.inner_iters, st.shift_rhs_iters, st.seconds)
 
 
-def band_energy_vjp(ctx: Context, pair: Pair, z, w, grad_E: float = 1.0, dH=None, dS=None, **opt):
+def band_energy_vjp(ctx: Context, pair: Pair, z, w, grad_E: float = 1.0, dH=None, dS=None, orbs=None, **opt):
     """Band energy over all orbitals and its gradients on the stored entries:
     dH += grad_E dE/dH_bc, dS += grad_E dE/dS_bc (zeros when not given).
     ``dH``/``dS`` may be numpy (host) or torch device tensors of shape
-    (nnzb, B, B).  Returns (dH, dS, E_band, info)."""
+    (nnzb, B, B).  ``orbs``: the columns c this call covers (default every
+    orbital); calls over a partition of the orbitals add up to the full
+    gradient, and the returned E_band is the sum of e_c over ``orbs``.
+    Returns (dH, dS, E_band, info)."""
     z = np.ascontiguousarray(z, dtype=np.complex128)
     w = np.ascontiguousarray(w, dtype=np.float64)
     K = z.shape[0]
+    if orbs is None:
+        norb, optr = pair.n, None
+    else:
+        orbs = np.ascontiguousarray(orbs, dtype=np.int64)
+        norb, optr = orbs.shape[0], _ptr(orbs, C.c_int64)
     opts = make_opts(**opt)
     shape = (pair.nnzb, pair.block, pair.block)
     if dH is None:
@@ -459,8 +467,8 @@ def band_energy_vjp(ctx: Context, pair: Pair, z, w, grad_E: float = 1.0, dH=None
         dH = np.ascontiguousarray(dH, dtype=np.float64)
         dS = np.ascontiguousarray(dS, dtype=np.float64)
     eb = C.c_double()
-    st, res, conv, _ = _stats(K, pair.n, False)
-    status = ctx.lib.gsc_band_energy_vjp(ctx.h, pair.h, K, _ptr(_complex_view(z)), _ptr(w), grad_E,
+    st, res, conv, _ = _stats(K, norb, False)
+    status = ctx.lib.gsc_band_energy_vjp(ctx.h, pair.h, K, _ptr(_complex_view(z)), _ptr(w), norb, optr, grad_E,
                                          C.byref(opts), _vp(dH), _vp(dS), C.byref(eb), mem, C.byref(st))
     L.check(status)
     info = dict(status=status, res=res, converged=conv.astype(bool), outer_iters=st.outer_iters,

@@ -742,8 +742,8 @@ gsc_status gsc_mulliken_band(gsc_ctx *ctx, const gsc_pair *pair, int nshift, con
 }
 
 gsc_status gsc_band_energy_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const double *z, const double *w,
-                               double grad_E, const gsc_opts *opts, double *dHval, double *dSval, double *e_band,
-                               int mem, gsc_stats *stats) {
+                               int norb, const int64_t *orb_idx, double grad_E, const gsc_opts *opts, double *dHval,
+                               double *dSval, double *e_band, int mem, gsc_stats *stats) {
     return guarded([&] {
         GSC_REQUIRE(ctx != nullptr && pair != nullptr, "ctx/pair must not be NULL");
         gsc_opts o;
@@ -759,6 +759,23 @@ gsc_status gsc_band_energy_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, c
         hipStream_t st = ctx->c.stream;
         const int64_t N = p.n;
         const int B = p.B;
+        // the columns this call covers
+        std::vector<int64_t> cols;
+        if (orb_idx == nullptr) {
+            GSC_REQUIRE(norb == N, "orb_idx == NULL needs norb == N (every orbital)");
+            cols.resize(N);
+            for (int64_t c = 0; c < N; ++c) cols[c] = c;
+        } else {
+            GSC_REQUIRE(norb >= 1, "norb must be >= 1");
+            std::vector<unsigned char> seen(N, 0);
+            cols.assign(orb_idx, orb_idx + norb);
+            for (const int64_t c : cols) {
+                GSC_REQUIRE(c >= 0 && c < N, "orbital index out of range");
+                GSC_REQUIRE(!seen[c], "orbital listed twice");
+                seen[c] = 1;
+            }
+        }
+        const int64_t R = static_cast<int64_t>(cols.size());
         o.carry = GSC_CARRY_PROJECTED;
         // projections of column c: every row b with a stored (b, c) entry,
         // i.e. the orbitals of the column blocks of c's block row (symmetric
@@ -773,34 +790,34 @@ gsc_status gsc_band_energy_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, c
         ProjSpec ps;
         ps.M = Mu;
         ps.srow = true;
-        ps.idx.assign(static_cast<size_t>(N) * Mu, 0);
+        ps.idx.assign(static_cast<size_t>(R) * Mu, 0);
         const int M = Mu + 1;
-        std::vector<int64_t> vidx(static_cast<size_t>(N) * M, -1);
-        for (int64_t c = 0; c < N; ++c) {
+        std::vector<int64_t> vidx(static_cast<size_t>(R) * M, -1);
+        for (int64_t r = 0; r < R; ++r) {
+            const int64_t c = cols[r];
             const int64_t I = c / B, a = c % B;
             int m = 0;
             for (int64_t blk = p.h_rowptr[I]; blk < p.h_rowptr[I + 1]; ++blk) {
                 const int64_t J = p.h_colidx[blk], mb = mirror[blk];
                 for (int be = 0; be < B; ++be, ++m) {
-                    ps.idx[static_cast<size_t>(c) * Mu + m] = static_cast<int32_t>(J * B + be);
-                    vidx[static_cast<size_t>(c) * M + m] = (mb * B + be) * B + a;
+                    ps.idx[static_cast<size_t>(r) * Mu + m] = static_cast<int32_t>(J * B + be);
+                    vidx[static_cast<size_t>(r) * M + m] = (mb * B + be) * B + a;
                 }
             }
-            for (; m < Mu; ++m) ps.idx[static_cast<size_t>(c) * Mu + m] = static_cast<int32_t>(c);
+            for (; m < Mu; ++m) ps.idx[static_cast<size_t>(r) * Mu + m] = static_cast<int32_t>(c);
         }
-        std::vector<int64_t> rhs(N);
-        for (int64_t c = 0; c < N; ++c) rhs[c] = c;
+        const std::vector<int64_t> &rhs = cols;
         std::vector<double> wE(nshift);
         for (int k = 0; k < nshift; ++k) wE[k] = w[k] * z[2 * k];
         DevBuf<double> dwE(nshift);
         GSC_HIP(hipMemcpyAsync(dwE.get(), wE.data(), nshift * 8, hipMemcpyHostToDevice, st));
-        DevBuf<c128> acc(static_cast<size_t>(N) * M * 3);
+        DevBuf<c128> acc(static_cast<size_t>(R) * M * 3);
         GSC_HIP(hipMemsetAsync(acc.get(), 0, acc.n * sizeof(c128), st));
         SolveRequest req;
         req.pair = &p;
         req.K = nshift;
         req.z = z;
-        req.R = static_cast<int>(N);
+        req.R = static_cast<int>(R);
         req.rhs_idx = rhs.data();
         req.opts = o;
         req.out_mem = GSC_MEM_DEVICE;
@@ -823,12 +840,12 @@ gsc_status gsc_band_energy_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, c
             pS = tS.get();
         }
         DevBuf<int64_t> dv(vidx.size());
-        DevBuf<double> ecol(N), eb(1);
+        DevBuf<double> ecol(R), eb(1);
         GSC_HIP(hipMemcpyAsync(dv.get(), vidx.data(), vidx.size() * 8, hipMemcpyHostToDevice, st));
-        const int64_t tot = N * M;
-        k_vjp_assemble<<<div_up(tot, 256), 256, 0, st>>>(static_cast<int>(N), M, acc.get(), dv.get(), grad_E, pH, pS,
+        const int64_t tot = R * M;
+        k_vjp_assemble<<<div_up(tot, 256), 256, 0, st>>>(static_cast<int>(R), M, acc.get(), dv.get(), grad_E, pH, pS,
                                                          ecol.get());
-        k_sum<<<1, 256, 0, st>>>(static_cast<int>(N), ecol.get(), eb.get());
+        k_sum<<<1, 256, 0, st>>>(static_cast<int>(R), ecol.get(), eb.get());
         GSC_HIP(hipGetLastError());
         if (mem != GSC_MEM_DEVICE) {
             GSC_HIP(hipMemcpyAsync(dHval, tH.get(), nv * 8, hipMemcpyDeviceToHost, st));

@@ -82,3 +82,35 @@ def test_autograd_forces_vs_oracle_and_fd(ctx):
         fd = -(e[0] - e[1]) / (2 * h)
         print(f"  atom {atom} ax {ax}: F={F[atom, ax]:.8e} fd={fd:.8e}", flush=True)
         assert fd == pytest.approx(F[atom, ax], rel=1e-5, abs=1e-7)
+
+
+def test_band_energy_vjp_slices_add_up(ctx):
+    """The backward over a partition of the orbitals (three uneven slices,
+    host and device gradients) adds up to the call over every orbital, and
+    each slice's energy is the sum of its orbitals' e_a from the forward."""
+    import torch
+    from paper_1002_1202_amd import api
+    c = configs.water_small(n_mol=16)
+    s = c["system"]
+    z = shift_grid(-40.0, -12.0, 20, 0.3)
+    w = trapezoid_weights(z)
+    print(f"case: vjp slices water N={s.n}", flush=True)
+    pair, _ = api.pair_from_system(ctx, s)
+    dH, dS, E, _ = api.band_energy_vjp(ctx, pair, z, w, tol=1e-12)
+    perm = np.random.default_rng(2).permutation(s.n)
+    parts = [perm[:7], perm[7:50], perm[50:]]
+    shape = (pair.nnzb, pair.block, pair.block)
+    sH = torch.zeros(shape, dtype=torch.float64, device="cuda:0")
+    sS = torch.zeros_like(sH)
+    _, e_orb, _, _ = api.mulliken_band(ctx, pair, z, w, np.arange(s.n), tol=1e-12)
+    Es = 0.0
+    for p in parts:
+        _, _, e, _ = api.band_energy_vjp(ctx, pair, z, w, 1.0, sH, sS, orbs=p, tol=1e-12)
+        assert abs(e - e_orb[p].sum()) <= 1e-9 * np.abs(e_orb[p]).sum()
+        Es += e
+    assert abs(Es - E) <= 1e-10 * abs(E)
+    assert rel(sH.cpu().numpy(), dH) < 1e-10 and rel(sS.cpu().numpy(), dS) < 1e-10
+    with pytest.raises(Exception, match="twice"):
+        api.band_energy_vjp(ctx, pair, z, w, orbs=np.array([3, 5, 3]))
+    with pytest.raises(Exception, match="range"):
+        api.band_energy_vjp(ctx, pair, z, w, orbs=np.array([s.n]))
