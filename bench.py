@@ -223,12 +223,21 @@ def lanczos_compare(ctx, cfg):
         best[name] = (t_best, out)
     tl, lz = best["lanczos"]
     tc, co = best["cocg_projected"]
+    # one more Lanczos run with every kernel timed (algorithmic bytes / time)
+    api.profile_enable(ctx, True)
+    api.lanczos_green(ctx, pair, z, rhs, m_max=4000, tol=tol, check_every=16, out="device")
+    prof = api.profile_read(ctx)
+    api.profile_enable(ctx, False)
+    kernels = {k: {"ms": round(v[0], 3), "launches": v[1], "GB": round(v[2] / 1e9, 3),
+                   "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
+               for k, v in prof.items() if v[1] > 0}
     g1 = lz.G_diag.cpu().numpy()
     g2 = co.G_proj[:, :, 0].cpu().numpy()
     return {"workload": f"{cfg['name']} G_jj: {len(rhs)} rhs x {len(z)} shifts, tol {tol:g}",
             "lanczos": {"seconds": tl, "steps_min": int(lz.steps.min()), "steps_max": int(lz.steps.max()),
                         "inner_iters": int(lz.inner_iters),
-                        "value": lz.shift_rhs_iters / tl, "unit": "shift·RHS·steps/s"},
+                        "value": lz.shift_rhs_iters / tl, "unit": "shift·RHS·steps/s",
+                        "kernels": kernels},
             "cocg_projected": {"seconds": tc, "outer_iters": int(co.outer_iters),
                                "value": co.shift_rhs_iters / tc, "unit": UNIT},
             "speedup_lanczos_vs_cocg": tc / tl,
@@ -476,10 +485,11 @@ def main():
     if dom in rocprof_summary.KERNEL_SOURCES and args.precision == "fp64":
         traffic = rocprof_summary.read_traffic(
             os.path.join(ROOT, "profiles", f"{cfg['name']}_{dom}_traffic.md"), dom)
-    kernels = {k: {"warmup_ms": round(v[0], 3), "launches": v[1], "GB": round(v[2] / 1e9, 3),
-                   "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
-               for k, v in pw.items() if v[1] > 0}
     copy_gbs = copy_bandwidth()
+    kernels = {k: {"warmup_ms": round(v[0], 3), "launches": v[1], "GB": round(v[2] / 1e9, 3),
+                   "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None,
+                   "frac_of_copy": round(v[2] / (v[0] * 1e-3) / 1e9 / copy_gbs, 3) if v[0] > 0 else None}
+               for k, v in pw.items() if v[1] > 0}
     line = {
         "metric": METRIC,
         "value": value,

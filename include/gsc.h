@@ -336,7 +336,8 @@ gsc_status gsc_band_energy_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, c
  * gsc_profile_enable(ctx, 1) resets the counters and turns timing on.
  * gsc_profile_read returns, for one kernel name ("spmm_seed", "spmm_S",
  * "shift_update", "cg_update", "cg_dir", "update_r", "rho_dot", "p_update",
- * "ctrl", "post", "proj_update", "cheb_step", "ring_transpose"), the summed
+ * "ctrl", "post", "proj_update", "cheb_step", "ring_transpose", and for the
+ * generalised Lanczos process "lz_hprod", "lz_update", "lz_scale"), the summed
  * device milliseconds, the number of launches and the summed algorithmic
  * bytes those launches must move (the method's own reads and writes, no re-reads).  GSC_E_ARG for an
  * unknown name. */

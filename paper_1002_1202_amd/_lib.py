@@ -94,7 +94,8 @@ SIGNATURES = {
 }
 
 KERNELS = ("spmm_seed", "spmm_S", "shift_update", "cg_update", "cg_dir", "update_r", "rho_dot",
-           "p_update", "ctrl", "post", "proj_update", "cheb_step", "ring_transpose")
+           "p_update", "ctrl", "post", "proj_update", "cheb_step", "ring_transpose", "lz_hprod",
+           "lz_update", "lz_scale")
 
 _lib = None
 

@@ -1632,7 +1632,7 @@ template <typename T> class TileSolver {
         const size_t Gs = static_cast<size_t>(td.Gs);
         int ran = 0;
         for (int n = 0; n < mmax; ++n) {
-            prof_.begin(st_, KP_SPMM_SEED, 2.0 * mat_bytes() + 3.0 * last_active_ * td.N * sizeof(cpx<T>));
+            prof_.begin(st_, KP_LZ_HPROD, 2.0 * mat_bytes() + 3.0 * last_active_ * td.N * sizeof(cpx<T>));
             launch_lz_hprod<T>(st_, pr_, td, Hv, Sv, u, t_.r.get(), s, cs.done, part.get());
             prof_.end(st_);
             k_lz_reduce_a<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, part.get(), n, mmax, a, steps, done.get());
@@ -1644,12 +1644,12 @@ template <typename T> class TileSolver {
                 k_copy_vec<T><<<div_up(NR, 256), 256, 0, st_>>>(NR, t_.r.get(), t_.d.get());
             }
             inner_solve(o, cs, v);
-            prof_.begin(st_, KP_UPDATE_R, 7.0 * last_active_ * td.N * sizeof(cpx<T>));
+            prof_.begin(st_, KP_LZ_UPDATE, 7.0 * last_active_ * td.N * sizeof(cpx<T>));
             k_lz_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, td.G, n, mmax, a, b, v, u, up, t_.r.get(), s, sp,
                                                part.get());
             prof_.end(st_);
             k_lz_reduce_b<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, part.get(), n, mmax, a, b, inv.get(), done.get());
-            prof_.begin(st_, KP_P_UPDATE, 2.0 * last_active_ * td.N * sizeof(cpx<T>));
+            prof_.begin(st_, KP_LZ_SCALE, 2.0 * last_active_ * td.N * sizeof(cpx<T>));
             k_lz_scale<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, inv.get(), v, up);
             prof_.end(st_);
             std::swap(u, up);
