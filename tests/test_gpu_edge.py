@@ -120,3 +120,46 @@ def test_rhs_counts_at_tile_boundaries(ctx, nrhs):
     assert rel(res.G_cols, X) < 1e-10
     resp = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, carry="projected", proj=rhs[:, None])
     assert rel(resp.G_proj[:, :, 0], X[:, np.arange(nrhs), rhs]) < 1e-10
+
+
+def test_empty_inputs_and_limits_are_rejected(ctx):
+    """Empty right-hand-side, shift and orbital lists and sizes beyond the
+    documented maxima are rejected before any device work: GSC_E_ARG from
+    the library, or ValueError where the binding cannot marshal the shape."""
+    from paper_1002_1202_amd import _lib, api
+    print("case: empty inputs and limits", flush=True)
+    c = configs.si_small(cells=(1, 1, 1), n_shift=4)
+    s = c["system"]
+    pair, _ = api.pair_from_system(ctx, s)
+    z = c["z"]
+    cases = {
+        "no rhs": lambda: api.solve(ctx, pair, z, rhs=np.zeros(0, np.int64)),
+        "no shifts": lambda: api.solve(ctx, pair, np.zeros(0, complex), rhs=[0]),
+        "no orbitals": lambda: api.mulliken_band(ctx, pair, z, np.ones(len(z)), np.zeros(0, np.int64)),
+        "fuse_steps 17": lambda: api.solve(ctx, pair, z, rhs=[0], fuse_steps=17),
+        "1025 projections": lambda: api.solve(ctx, pair, z, rhs=[0], carry="projected",
+                                              proj=np.zeros((1, 1025), np.int64)),
+        "lanczos m_max 0": lambda: api.lanczos_green(ctx, pair, z, [0], m_max=0),
+    }
+    for name, call in cases.items():
+        with pytest.raises((_lib.GscError, ValueError)) as e:
+            call()
+        if isinstance(e.value, _lib.GscError):
+            assert e.value.status == -1, name
+
+
+def test_maximum_projection_count(ctx):
+    """1024 projections per right-hand side (the maximum): every orbital of
+    a 64-atom cell four times over, against the dense LU."""
+    from paper_1002_1202_amd import api
+    print("case: 1024 projections", flush=True)
+    c = configs.si_small(cells=(2, 2, 2), n_shift=5, eta=0.2, seed=8)
+    s = c["system"]
+    S, H, _ = oased.dense_pair(s)
+    pair, _ = api.pair_from_system(ctx, s)
+    rhs = c["rhs"][:3]
+    proj = np.tile(np.concatenate([np.arange(s.n), np.arange(s.n)[::-1]]), 2)[None, :1024].repeat(3, 0)
+    res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, carry="projected", proj=proj)
+    X = ogreen.solve_dense(H, S, c["z"], rhs)
+    ref = np.take_along_axis(X, np.broadcast_to(proj[None], (X.shape[0],) + proj.shape), axis=2)
+    assert rel(res.G_proj, ref) < 1e-10
