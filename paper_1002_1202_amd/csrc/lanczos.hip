@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kBlock) void k_lz_hprod(int nb, int Rp, int Lb, int
                 const T *sb = Sv + static_cast<size_t>(b) * B * B;
                 cpx<T> xv[B];
 #pragma unroll
-                for (int c = 0; c < B; ++c) xv[c] = act ? u[static_cast<size_t>(J * B + c) * Rp + col] : cpx<T>{0, 0};
+                for (int c = 0; c < B; ++c) xv[c] = u[static_cast<size_t>(J * B + c) * Rp + col];
                 if (J == I) {
 #pragma unroll
                     for (int c = 0; c < B; ++c) own[c] = xv[c];

@@ -43,10 +43,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_seed(
                 const int J = colidx[b];
                 const T *sb = Sv + static_cast<size_t>(b) * B * B;
                 const T *hb = Hv + static_cast<size_t>(b) * B * B;
+                // loaded for every lane: the column index is inside the padded
+                // tile, and inactive lanes' sums are never stored
                 cpx<T> x[B];
 #pragma unroll
-                for (int c = 0; c < B; ++c)
-                    x[c] = act ? p[static_cast<size_t>(J * B + c) * Rp + col] : cpx<T>{0, 0};
+                for (int c = 0; c < B; ++c) x[c] = p[static_cast<size_t>(J * B + c) * Rp + col];
 #pragma unroll
                 for (int a = 0; a < B; ++a) {
 #pragma unroll
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_S(
                 cpx<T> x[B];
 #pragma unroll
                 for (int c = 0; c < B; ++c)
-                    x[c] = act ? d[static_cast<size_t>(J * B + c) * Rp + col] : cpx<T>{0, 0};
+                    x[c] = d[static_cast<size_t>(J * B + c) * Rp + col];
                 if (J == I) {
 #pragma unroll
                     for (int c = 0; c < B; ++c) own[c] = x[c];
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_seed_cl(
                 cpx<T> x[B];
 #pragma unroll
                 for (int c = 0; c < B; ++c)
-                    x[c] = act ? p[static_cast<size_t>(J * B + c) * Rp + col] : cpx<T>{0, 0};
+                    x[c] = p[static_cast<size_t>(J * B + c) * Rp + col];
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     const int b = cblk[u * C + i];
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_S_cl(
                 cpx<T> x[B];
 #pragma unroll
                 for (int c = 0; c < B; ++c)
-                    x[c] = act ? d[static_cast<size_t>(J * B + c) * Rp + col] : cpx<T>{0, 0};
+                    x[c] = d[static_cast<size_t>(J * B + c) * Rp + col];
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     const int b = cblk[u * C + i];
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
                 cpx<T> xv[B];
 #pragma unroll
                 for (int c = 0; c < B; ++c)
-                    xv[c] = act ? x[static_cast<size_t>(J * B + c) * Rp + col] : cpx<T>{0, 0};
+                    xv[c] = x[static_cast<size_t>(J * B + c) * Rp + col];
                 if (J == I) {
 #pragma unroll
                     for (int c = 0; c < B; ++c) own[c] = xv[c];

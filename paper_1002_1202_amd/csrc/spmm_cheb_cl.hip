@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_cl(
             cpx<T> xv[B];
 #pragma unroll
             for (int cc = 0; cc < B; ++cc)
-                xv[cc] = act ? x[static_cast<size_t>(J * B + cc) * Rp + col] : cpx<T>{0, 0};
+                xv[cc] = x[static_cast<size_t>(J * B + cc) * Rp + col];
 #pragma unroll
             for (int i = 0; i < C; ++i) {
                 if (mask & (1u << i)) {

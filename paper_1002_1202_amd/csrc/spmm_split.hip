@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_split(
                 cpx<T> xv[H];
 #pragma unroll
                 for (int c = 0; c < H; ++c)
-                    xv[c] = act ? x[static_cast<size_t>(J * B + h0 + c) * Rp + col] : cpx<T>{0, 0};
+                    xv[c] = x[static_cast<size_t>(J * B + h0 + c) * Rp + col];
                 if (J == I) {
 #pragma unroll
                     for (int c = 0; c < H; ++c) own[c] = xv[c];
