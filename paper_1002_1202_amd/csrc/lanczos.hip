@@ -37,14 +37,20 @@ __global__ __launch_bounds__(kBlock) void k_lz_hprod(int nb, int Rp, int Lb, int
 #pragma unroll
             for (int a = 0; a < B; ++a) { acc[a] = {0, 0}; accs[a] = {0, 0}; own[a] = {0, 0}; }
             const int b0 = rowptr[I], b1 = rowptr[I + 1];
+            // loads of finished processes are masked off (their lines are not
+            // fetched); their registers keep stale values that are never used
+            cpx<T> xv[B];
+#pragma unroll
+            for (int c = 0; c < B; ++c) xv[c] = {0, 0};
 #pragma unroll 2
             for (int b = b0; b < b1; ++b) {
                 const int J = colidx[b];
                 const T *hb = Hv + static_cast<size_t>(b) * B * B;
                 const T *sb = Sv + static_cast<size_t>(b) * B * B;
-                cpx<T> xv[B];
+                if (act) {
 #pragma unroll
-                for (int c = 0; c < B; ++c) xv[c] = u[static_cast<size_t>(J * B + c) * Rp + col];
+                    for (int c = 0; c < B; ++c) xv[c] = u[static_cast<size_t>(J * B + c) * Rp + col];
+                }
                 if (J == I) {
 #pragma unroll
                     for (int c = 0; c < B; ++c) own[c] = xv[c];

@@ -38,16 +38,20 @@ __global__ __launch_bounds__(kBlock) void k_spmm_seed(
 #pragma unroll
             for (int a = 0; a < B; ++a) { aS[a] = {0, 0}; aH[a] = {0, 0}; }
             const int b0 = rowptr[I], b1 = rowptr[I + 1];
+            // loads of finished columns are masked off (their lines are not
+            // fetched); their registers keep stale values that are never used
+            cpx<T> x[B];
+#pragma unroll
+            for (int c = 0; c < B; ++c) x[c] = {0, 0};
 #pragma unroll 2
             for (int b = b0; b < b1; ++b) {
                 const int J = colidx[b];
                 const T *sb = Sv + static_cast<size_t>(b) * B * B;
                 const T *hb = Hv + static_cast<size_t>(b) * B * B;
-                // loaded for every lane: the column index is inside the padded
-                // tile, and inactive lanes' sums are never stored
-                cpx<T> x[B];
+                if (act) {
 #pragma unroll
-                for (int c = 0; c < B; ++c) x[c] = p[static_cast<size_t>(J * B + c) * Rp + col];
+                    for (int c = 0; c < B; ++c) x[c] = p[static_cast<size_t>(J * B + c) * Rp + col];
+                }
 #pragma unroll
                 for (int a = 0; a < B; ++a) {
 #pragma unroll
@@ -106,14 +110,19 @@ __global__ __launch_bounds__(kBlock) void k_spmm_S(
 #pragma unroll
             for (int a = 0; a < B; ++a) { aS[a] = {0, 0}; own[a] = {0, 0}; }
             const int b0 = rowptr[I], b1 = rowptr[I + 1];
+            // loads of finished columns are masked off (their lines are not
+            // fetched); their registers keep stale values that are never used
+            cpx<T> x[B];
+#pragma unroll
+            for (int c = 0; c < B; ++c) x[c] = {0, 0};
 #pragma unroll 2
             for (int b = b0; b < b1; ++b) {
                 const int J = colidx[b];
                 const T *sb = Sv + static_cast<size_t>(b) * B * B;
-                cpx<T> x[B];
+                if (act) {
 #pragma unroll
-                for (int c = 0; c < B; ++c)
-                    x[c] = d[static_cast<size_t>(J * B + c) * Rp + col];
+                    for (int c = 0; c < B; ++c) x[c] = d[static_cast<size_t>(J * B + c) * Rp + col];
+                }
                 if (J == I) {
 #pragma unroll
                     for (int c = 0; c < B; ++c) own[c] = x[c];
@@ -330,14 +339,19 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
 #pragma unroll
             for (int a = 0; a < B; ++a) { aS[a] = {0, 0}; own[a] = {0, 0}; }
             const int b0 = rowptr[I], b1 = rowptr[I + 1];
+            // loads of finished columns are masked off (their lines are not
+            // fetched); their registers keep stale values that are never used
+            cpx<T> xv[B];
+#pragma unroll
+            for (int c = 0; c < B; ++c) xv[c] = {0, 0};
 #pragma unroll 2
             for (int b = b0; b < b1; ++b) {
                 const int J = colidx[b];
                 const T *sb = Sv + static_cast<size_t>(b) * B * B;
-                cpx<T> xv[B];
+                if (act) {
 #pragma unroll
-                for (int c = 0; c < B; ++c)
-                    xv[c] = x[static_cast<size_t>(J * B + c) * Rp + col];
+                    for (int c = 0; c < B; ++c) xv[c] = x[static_cast<size_t>(J * B + c) * Rp + col];
+                }
                 if (J == I) {
 #pragma unroll
                     for (int c = 0; c < B; ++c) own[c] = xv[c];
