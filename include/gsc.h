@@ -106,7 +106,13 @@ typedef struct {
                               vectors are loaded and stored with the default
                               cache policy, 2: nontemporal (kept out of L2 so
                               the gathered halo stays resident)               */
-    int reserved[4];
+    int cheb_block;        /* [0 = auto] columns per Chebyshev launch block (a
+                              multiple of 64, row layout): every step of the
+                              inner solve runs on one block of columns at a
+                              time; auto sizes the block so that the step's
+                              three vectors fit the 256 MB infinity cache
+                              (no blocking when the tile already fits)        */
+    int reserved[3];
 } gsc_opts;
 
 /* Statistics.  The three arrays are caller-owned HOST arrays of

@@ -22,7 +22,8 @@ class Opts(C.Structure):
                 ("inner_max_iter", C.c_int), ("precision", C.c_int), ("carry", C.c_int),
                 ("seed_index", C.c_int), ("fuse_steps", C.c_int), ("rhs_tile", C.c_int),
                 ("recheck", C.c_int), ("spmm_kernel", C.c_int), ("inner_method", C.c_int),
-                ("graph_iters", C.c_int), ("stream_hint", C.c_int), ("reserved", C.c_int * 4)]
+                ("graph_iters", C.c_int), ("stream_hint", C.c_int), ("cheb_block", C.c_int),
+                ("reserved", C.c_int * 3)]
 
 
 class Stats(C.Structure):

@@ -66,6 +66,7 @@ struct TileDims {
     int variant = 1;          // SpMM kernel: 0 one block row per wave, 1 register-blocked clusters,
                               // 2 slabs, 3 split-orbital 32-column stripes (Chebyshev step)
     bool nt = false;          // streamed vectors of the Chebyshev step bypass L2 retention
+    int cb = 0;               // columns per Chebyshev column block (multiple of 64; Rp: one block)
 };
 
 // XCD-aware remap of the linear block id: blocks l = x + gx*y are dispatched

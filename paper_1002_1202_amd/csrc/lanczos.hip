@@ -16,7 +16,7 @@
 namespace gsc {
 
 template <typename T, int B>
-__global__ __launch_bounds__(kBlock) void k_lz_hprod(int nb, int Rp, int Lb, int Gs,
+__global__ __launch_bounds__(kBlock) void k_lz_hprod(int nb, int Rp, int Gs,
                                                      const int32_t *__restrict__ rowptr,
                                                      const int32_t *__restrict__ colidx, const T *__restrict__ Hv,
                                                      const T *__restrict__ Sv, const cpx<T> *__restrict__ u,
@@ -29,10 +29,13 @@ __global__ __launch_bounds__(kBlock) void k_lz_hprod(int nb, int Rp, int Lb, int
     const int col = cx * 64 + lane;
     const bool act = !skip[col];
     double dre = 0.0, dim = 0.0, nrm = 0.0;
-    const int I0 = g * Lb;
-    const int I1 = min(nb, I0 + Lb);
+    // rows of this wave: every row group takes one row per wave per step, so
+    // the groups advance together (step i covers rows [i*4*Gs, (i+1)*4*Gs))
+    // and the rows in flight on an XCD stay within one window, however many
+    // rows a group holds
+    const int row_step = kWavesPerBlock * Gs;
     if (__ballot(act) != 0) {
-        for (int I = I0 + wv; I < I1; I += kWavesPerBlock) {
+        for (int I = kWavesPerBlock * g + wv; I < nb; I += row_step) {
             cpx<T> acc[B], accs[B], own[B];
 #pragma unroll
             for (int a = 0; a < B; ++a) { acc[a] = {0, 0}; accs[a] = {0, 0}; own[a] = {0, 0}; }
@@ -99,10 +102,10 @@ void launch_lz_hprod(hipStream_t st, const Pair &pr, const TileDims &td, const T
                      cpx<T> *h, cpx<T> *su, const int *skip, double *part) {
     dim3 grid(td.Rp / 64, td.Gs), block(kBlock);
     if (pr.B == 4)
-        k_lz_hprod<T, 4><<<grid, block, 0, st>>>(static_cast<int>(pr.nb), td.Rp, td.Lb, td.Gs, pr.rowptr.get(),
+        k_lz_hprod<T, 4><<<grid, block, 0, st>>>(static_cast<int>(pr.nb), td.Rp, td.Gs, pr.rowptr.get(),
                                                  pr.colidx.get(), Hv, Sv, u, h, su, skip, part);
     else
-        k_lz_hprod<T, 6><<<grid, block, 0, st>>>(static_cast<int>(pr.nb), td.Rp, td.Lb, td.Gs, pr.rowptr.get(),
+        k_lz_hprod<T, 6><<<grid, block, 0, st>>>(static_cast<int>(pr.nb), td.Rp, td.Gs, pr.rowptr.get(),
                                                  pr.colidx.get(), Hv, Sv, u, h, su, skip, part);
     GSC_HIP(hipGetLastError());
 }

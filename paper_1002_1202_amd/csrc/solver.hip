@@ -27,6 +27,10 @@
 
 namespace gsc {
 
+// budget of the Chebyshev column blocks' streamed vectors (of the 256 MB
+// infinity cache)
+constexpr double kChebBlockBytes = 224.0e6;
+
 // ------------------------------------------------------------------ helpers
 template <typename V>
 __device__ inline V block_sum(V v, V *lds) {
@@ -1353,7 +1357,17 @@ template <typename T> class TileSolver {
         td.Lr = div_up(td.N, td.G);
         {
             const int k = req.opts.spmm_kernel;
-            set_spmm_geometry(td, pr_, k == 2 ? 1 : k == 3 ? 2 : k == 4 ? 3 : 0);
+            const int variant = k == 2 ? 1 : k == 3 ? 2 : k == 4 ? 3 : 0;
+            // columns per Chebyshev launch: all steps of the inner solve run
+            // on one column block at a time, sized so that the three vectors
+            // the step streams (y_k, y_{k-1}, r) stay in the 256 MB infinity
+            // cache between steps and the gather's re-reads hit it; blocks
+            // of at least two 64-column chunks, row layout only
+            const int cb = req.opts.cheb_block > 0
+                               ? req.opts.cheb_block
+                               : static_cast<int>(kChebBlockBytes / (3.0 * td.N * sizeof(cpx<T>))) / 64 * 64;
+            td.cb = (variant == 0 && cb >= (req.opts.cheb_block > 0 ? 64 : 128) && cb < Rp) ? cb : Rp;
+            set_spmm_geometry(td, pr_, variant);
             td.nt = req.opts.stream_hint == 2;
         }
         st_ = ctx_.stream;
@@ -1895,7 +1909,7 @@ template <typename T> class TileSolver {
         buf[K % 2] = ytarget;
         buf[(K + 1) % 2] = t_.w.get();
         double rho_prev = 1.0 / sigma;
-        auto step = [&](int kk, const int *skip) {
+        auto step = [&](int kk, const int *skip, int c0, int w) {
             const double rho = 1.0 / (2.0 * sigma - rho_prev);
             const double c1 = rho * rho_prev, c2 = 2.0 * rho / cheb_delta_;
             const int mode = kk == 1 ? 0 : kk == 2 ? 1 : 2;
@@ -1903,25 +1917,29 @@ template <typename T> class TileSolver {
                 launch_cheb_cl<T>(st_, pr_, td, mode, t_.scl.get(), buf[kk % 2], t_.r.get(), buf[(kk + 1) % 2], skip,
                                   1.0 / cheb_theta_, c1, c2, t_.part_d.get());
             else
-                launch_cheb_step<T>(st_, pr_, td, mode, Sv, buf[kk % 2], t_.r.get(), buf[(kk + 1) % 2], skip,
-                                    1.0 / cheb_theta_, c1, c2, t_.part_d.get());
+                launch_cheb_step<T>(st_, pr_, td, mode, c0, w, Sv, buf[kk % 2], t_.r.get(), buf[(kk + 1) % 2],
+                                    skip, 1.0 / cheb_theta_, c1, c2, t_.part_d.get());
             rho_prev = rho;
         };
-        // the K - 1 steps run back to back: one event pair times them all
+        // the K - 1 steps of each column block run back to back (columns are
+        // independent); one event pair times them all
         const double vec = static_cast<double>(last_active_) * td.N * sizeof(cpx<T>);
         double bytes = 0.0;
+        for (int k = 1; k < K; ++k) bytes += vec * (k == 1 ? 2 : k == 2 ? 3 : 4);
+        const int cb = td.cb > 0 ? td.cb : td.Rp;
+        int launches = 0;
         prof_.begin_group(st_, KP_CHEB);
-        for (int k = 1; k < K; ++k) {
-            step(k, t_.c_done.get());
-            bytes += vec * (k == 1 ? 2 : k == 2 ? 3 : 4);
+        for (int c0 = 0; c0 < td.Rp; c0 += cb) {
+            rho_prev = 1.0 / sigma;
+            for (int k = 1; k < K; ++k, ++launches) step(k, t_.c_done.get(), c0, std::min(cb, td.Rp - c0));
         }
-        prof_.end_group(st_, K - 1, bytes);
+        prof_.end_group(st_, launches, bytes);
         k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_ / cheb_rho_, 0, cs);
         // extra steps for the columns that failed the check (bytes counted
         // from the check's outcome are not known here: counted as zero)
         prof_.begin_group(st_, KP_CHEB);
-        step(K, t_.c_inner_done.get());
-        step(K + 1, t_.c_inner_done.get());
+        step(K, t_.c_inner_done.get(), 0, td.Rp);
+        step(K + 1, t_.c_inner_done.get(), 0, td.Rp);
         prof_.end_group(st_, 2, 0.0);
         k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_, 1, cs);
         GSC_HIP(hipGetLastError());

@@ -17,7 +17,7 @@ namespace gsc {
 // eq. CGp:r with the S-bilinear form) of this row group.
 template <typename T, int B>
 __global__ __launch_bounds__(kBlock) void k_spmm_seed(
-    int nb, int Rp, int Lb, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    int nb, int Rp, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const T *__restrict__ Sv, const T *__restrict__ Hv, const cpx<T> *__restrict__ p,
     cpx<T> *__restrict__ q, const c128 *__restrict__ z, const int *__restrict__ seed,
     const int *__restrict__ skip, c128 *__restrict__ partial) {
@@ -30,10 +30,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm_seed(
     c128 zs = act ? z[seed[col]] : c128{0, 0};
     const cpx<T> zt = ccast<T>(zs);
     c128 dot{0.0, 0.0};
-    const int I0 = g * Lb;
-    const int I1 = min(nb, I0 + Lb);
+    // rows of this wave: every row group takes one row per wave per step, so
+    // the groups advance together (step i covers rows [i*4*Gs, (i+1)*4*Gs))
+    // and the rows in flight on an XCD stay within one window, however many
+    // rows a group holds
+    const int row_step = kWavesPerBlock * static_cast<int>(gridDim.y);
     if (__ballot(act) != 0) {
-        for (int I = I0 + w; I < I1; I += kWavesPerBlock) {
+        for (int I = kWavesPerBlock * g + w; I < nb; I += row_step) {
             cpx<T> aS[B], aH[B];
 #pragma unroll
             for (int a = 0; a < B; ++a) { aS[a] = {0, 0}; aH[a] = {0, 0}; }
@@ -92,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_seed(
 // per-column partial  Re(d^H S d)  (the CG curvature; S real symmetric).
 template <typename T, int B>
 __global__ __launch_bounds__(kBlock) void k_spmm_S(
-    int nb, int Rp, int Lb, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    int nb, int Rp, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const T *__restrict__ Sv, const cpx<T> *__restrict__ d, cpx<T> *__restrict__ wout,
     const int *__restrict__ skip, double *__restrict__ partial) {
     int cx, g;
@@ -102,10 +105,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm_S(
     const int col = cx * 64 + lane;
     const bool act = !skip[col];
     double dot = 0.0;
-    const int I0 = g * Lb;
-    const int I1 = min(nb, I0 + Lb);
+    // rows of this wave: every row group takes one row per wave per step, so
+    // the groups advance together (step i covers rows [i*4*Gs, (i+1)*4*Gs))
+    // and the rows in flight on an XCD stay within one window, however many
+    // rows a group holds
+    const int row_step = kWavesPerBlock * static_cast<int>(gridDim.y);
     if (__ballot(act) != 0) {
-        for (int I = I0 + wv; I < I1; I += kWavesPerBlock) {
+        for (int I = kWavesPerBlock * g + wv; I < nb; I += row_step) {
             cpx<T> aS[B], own[B];
 #pragma unroll
             for (int a = 0; a < B; ++a) { aS[a] = {0, 0}; own[a] = {0, 0}; }
@@ -316,10 +322,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_S_cl(
 // [theta - delta, theta + delta] fused with the product, in the three-term
 // form (see cheb_update): one gathered vector (y_k, or r in the first
 // step), r and y_{k-1} streamed, y_{k+1} written over y_{k-1}, and a
-// partial ||r - S y_k||^2.
+// partial ||r - S y_k||^2.  A launch covers the columns [col0, col0 +
+// 64 gridDim.x) of the Rp-wide tile.
 template <typename T, int B, int MODE, bool NT>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(
-    int nb, int Rp, int Lb, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    int nb, int Rp, int col0, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const T *__restrict__ Sv, const cpx<T> *__restrict__ y, const cpx<T> *__restrict__ r,
     cpx<T> *__restrict__ yio, const int *__restrict__ skip, T inv_theta, T c1, T c2,
     double *__restrict__ partial) {
@@ -327,14 +334,17 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
     xcd_remap_chunks(cx, g);
     const int lane = threadIdx.x & 63;
     const int wv = wave_id();
-    const int col = cx * 64 + lane;
+    const int col = col0 + cx * 64 + lane;
     const bool act = !skip[col];
     double acc2 = 0.0;
-    const int I0 = g * Lb;
-    const int I1 = min(nb, I0 + Lb);
+    // rows of this wave: every row group takes one row per wave per step, so
+    // the groups advance together (step i covers rows [i*4*Gs, (i+1)*4*Gs))
+    // and the rows in flight on an XCD stay within one window, however many
+    // rows a group holds
+    const int row_step = kWavesPerBlock * static_cast<int>(gridDim.y);
     const cpx<T> *x = MODE == 0 ? r : y;
     if (__ballot(act) != 0) {
-        for (int I = I0 + wv; I < I1; I += kWavesPerBlock) {
+        for (int I = kWavesPerBlock * g + wv; I < nb; I += row_step) {
             cpx<T> aS[B], own[B];
 #pragma unroll
             for (int a = 0; a < B; ++a) { aS[a] = {0, 0}; own[a] = {0, 0}; }
@@ -385,9 +395,12 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
 }
 
 template <typename T>
-void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, int mode, const T *Sv,
-                      const cpx<T> *y, const cpx<T> *r, cpx<T> *yio, const int *skip, double inv_theta,
-                      double c1, double c2, double *partial) {
+void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, int mode, int col0, int ncols,
+                      const T *Sv, const cpx<T> *y, const cpx<T> *r, cpx<T> *yio, const int *skip,
+                      double inv_theta, double c1, double c2, double *partial) {
+    GSC_REQUIRE(col0 % 64 == 0 && ncols % 64 == 0 && ncols > 0 && col0 + ncols <= td.Rp,
+                "Chebyshev column block outside the tile");
+    GSC_REQUIRE(td.variant == 0 || (col0 == 0 && ncols == td.Rp), "column blocks need the row layout");
     if (td.variant == 2) {
         launch_cheb_slab<T>(st, pr, td, mode, Sv, y, r, yio, skip, inv_theta, c1, c2, partial);
         return;
@@ -396,11 +409,11 @@ void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, int mo
         launch_cheb_split<T>(st, pr, td, mode, Sv, y, r, yio, skip, inv_theta, c1, c2, partial);
         return;
     }
-    // the fused step uses the one-block-row-per-wave layout (td.Lb rows per group)
-    dim3 grid(td.Rp / 64, td.Gs), block(kBlock);
+    // the fused step uses the row layout (one block row per wave and step)
+    dim3 grid(ncols / 64, td.Gs), block(kBlock);
     const T it = static_cast<T>(inv_theta), a = static_cast<T>(c1), b = static_cast<T>(c2);
 #define GSC_CHEB(BB, M, N)                                                                                      \
-    k_cheb_step<T, BB, M, N><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(), Sv, \
+    k_cheb_step<T, BB, M, N><<<grid, block, 0, st>>>(td.nb, td.Rp, col0, pr.rowptr.get(), pr.colidx.get(), Sv, \
                                                      y, r, yio, skip, it, a, b, partial)
 #define GSC_CHEB_N(BB, M) \
     if (td.nt) GSC_CHEB(BB, M, true); else GSC_CHEB(BB, M, false);
@@ -413,11 +426,12 @@ void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, int mo
     GSC_HIP(hipGetLastError());
 }
 
-template void launch_cheb_step<double>(hipStream_t, const Pair &, const TileDims &, int, const double *,
+template void launch_cheb_step<double>(hipStream_t, const Pair &, const TileDims &, int, int, int, const double *,
                                        const c128 *, const c128 *, c128 *, const int *, double, double, double,
                                        double *);
-template void launch_cheb_step<float>(hipStream_t, const Pair &, const TileDims &, int, const float *, const c64 *,
-                                      const c64 *, c64 *, const int *, double, double, double, double *);
+template void launch_cheb_step<float>(hipStream_t, const Pair &, const TileDims &, int, int, int, const float *,
+                                      const c64 *, const c64 *, c64 *, const int *, double, double, double,
+                                      double *);
 
 // ------------------------------------------------------------------ launchers
 // Row-group geometry of the product kernels.  Every reduction of their
@@ -440,8 +454,13 @@ void set_spmm_geometry(TileDims &td, const Pair &pr, int variant) {
         td.Gs = (std::max(g, 1) + 7) / 8 * 8;
     } else {
         // one block row per wave where the rows allow: the rows a sweep
-        // keeps in flight then span few x-planes, whose halo fits L2
-        int g = std::max(1, 4096 / std::max(1, td.Rp / 64));
+        // keeps in flight then span few x-planes, whose halo fits L2.  With
+        // more than 8 column chunks an XCD would run the row groups of
+        // several chunks at once (each with its own x window) unless the
+        // groups of one chunk fill it: at least 256 groups then.
+        const int w = td.cb > 0 && td.cb < td.Rp ? td.cb : td.Rp;   // width of a Chebyshev launch
+        int g = std::max(1, 4096 / std::max(1, w / 64));
+        if (w / 64 > 8) g = std::max(g, 256);
         g = static_cast<int>(std::min<int64_t>(g, (td.nb + 3) / 4));
         td.Gs = (std::max(g, 1) + 7) / 8 * 8;
     }
@@ -476,10 +495,10 @@ void launch_spmm_seed(hipStream_t st, const Pair &pr, const TileDims &td, const 
         return;
     }
     if (pr.B == 4)
-        k_spmm_seed<T, 4><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(),
+        k_spmm_seed<T, 4><<<grid, block, 0, st>>>(td.nb, td.Rp, pr.rowptr.get(), pr.colidx.get(),
                                                   Sv, Hv, p, q, z, seed, skip, partial);
     else
-        k_spmm_seed<T, 6><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(),
+        k_spmm_seed<T, 6><<<grid, block, 0, st>>>(td.nb, td.Rp, pr.rowptr.get(), pr.colidx.get(),
                                                   Sv, Hv, p, q, z, seed, skip, partial);
     GSC_HIP(hipGetLastError());
 }
@@ -505,10 +524,10 @@ void launch_spmm_S(hipStream_t st, const Pair &pr, const TileDims &td, const T *
         return;
     }
     if (pr.B == 4)
-        k_spmm_S<T, 4><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(), Sv,
+        k_spmm_S<T, 4><<<grid, block, 0, st>>>(td.nb, td.Rp, pr.rowptr.get(), pr.colidx.get(), Sv,
                                                d, w, skip, partial);
     else
-        k_spmm_S<T, 6><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(), Sv,
+        k_spmm_S<T, 6><<<grid, block, 0, st>>>(td.nb, td.Rp, pr.rowptr.get(), pr.colidx.get(), Sv,
                                                d, w, skip, partial);
     GSC_HIP(hipGetLastError());
 }

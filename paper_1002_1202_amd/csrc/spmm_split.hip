@@ -20,7 +20,7 @@ __device__ inline cpx<T> swap_halves(cpx<T> v) {
 
 template <typename T, int B, int MODE, bool NT>
 __global__ __launch_bounds__(kBlock) void k_cheb_split(
-    int nb, int Rp, int Lb, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    int nb, int Rp, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const T *__restrict__ Sv, const cpx<T> *__restrict__ y, const cpx<T> *__restrict__ r, cpx<T> *__restrict__ yio,
     const int *__restrict__ skip, T inv_theta, T c1, T c2, double *__restrict__ partial) {
     constexpr int H = B / 2;
@@ -33,11 +33,12 @@ __global__ __launch_bounds__(kBlock) void k_cheb_split(
     const int col = cx * 32 + (lane & 31);
     const bool act = !skip[col];
     double acc2 = 0.0;
-    const int I0 = g * Lb;
-    const int I1 = min(nb, I0 + Lb);
+    // rows of this wave: every row group takes one row per wave per step, so
+    // the groups advance together (step i covers rows [i*4*Gs, (i+1)*4*Gs))
+    const int row_step = kWavesPerBlock * static_cast<int>(gridDim.y);
     const cpx<T> *x = MODE == 0 ? r : y;
     if (__ballot(act) != 0) {
-        for (int I = I0 + wv; I < I1; I += kWavesPerBlock) {
+        for (int I = kWavesPerBlock * g + wv; I < nb; I += row_step) {
             cpx<T> aS[B], own[H];
 #pragma unroll
             for (int a = 0; a < B; ++a) aS[a] = {0, 0};
@@ -104,7 +105,7 @@ void launch_cheb_split(hipStream_t st, const Pair &pr, const TileDims &td, int m
     dim3 grid(td.Rp / 32, td.Gs), block(kBlock);
     const T it = static_cast<T>(inv_theta), a = static_cast<T>(c1), b = static_cast<T>(c2);
 #define GSC_CHEB_SP(BB, M, N)                                                                                       \
-    k_cheb_split<T, BB, M, N><<<grid, block, 0, st>>>(td.nb, td.Rp, td.Lb, pr.rowptr.get(), pr.colidx.get(), Sv, y, \
+    k_cheb_split<T, BB, M, N><<<grid, block, 0, st>>>(td.nb, td.Rp, pr.rowptr.get(), pr.colidx.get(), Sv, y, \
                                                       r, yio, skip, it, a, b, partial)
 #define GSC_CHEB_SP_N(BB, M) \
     if (td.nt) GSC_CHEB_SP(BB, M, true); else GSC_CHEB_SP(BB, M, false);
