@@ -441,7 +441,6 @@ void set_spmm_geometry(TileDims &td, const Pair &pr, int variant) {
     if (variant == 2) {
         // slab kernels: one block row per wave, 4 per workgroup
         td.Gs = slab_groups(td.nb);
-        td.Lb = kWavesPerBlock;
         return;
     }
     if (variant == 1) {
@@ -464,7 +463,6 @@ void set_spmm_geometry(TileDims &td, const Pair &pr, int variant) {
         g = static_cast<int>(std::min<int64_t>(g, (td.nb + 3) / 4));
         td.Gs = (std::max(g, 1) + 7) / 8 * 8;
     }
-    td.Lb = div_up(td.nb, td.Gs);
 }
 
 inline void cluster_geometry(const Pair &pr, const TileDims &td, int &gy, int &Lc) {
