@@ -382,6 +382,9 @@ def main():
     ap.add_argument("--inner", type=int, default=0, help="0 auto, 1 CG, 2 Chebyshev")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate launch shapes on this problem first and use the fastest")
+    ap.add_argument("--only", default=None, choices=["batched", "lanczos"],
+                    help="instead of the throughput line: only the batched mixed-vs-FP64 comparison or only "
+                         "the Lanczos-vs-COCG comparison (its own JSON line; for per-workload profiles)")
     ap.add_argument("--forces", default=None, choices=["slab8192", "water3000"],
                     help="instead of the throughput line: one band energy + forces step over every "
                          "orbital of a full-size workload (its own JSON line)")
@@ -416,6 +419,12 @@ def main():
         del a, b
     if args.forces:
         print(json.dumps(forces_measure(args.forces, precision=args.forces_precision)), flush=True)
+        return
+    if args.only == "batched":
+        print(json.dumps(batched_compare(api.Context(0))), flush=True)
+        return
+    if args.only == "lanczos":
+        print(json.dumps(lanczos_compare(api.Context(0), workload(args.workload))), flush=True)
         return
     cfg = workload(args.workload)
     if args.tol is None:

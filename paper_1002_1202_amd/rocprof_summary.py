@@ -44,6 +44,7 @@ def source_digest(name: str) -> str:
 
 
 def _short(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "")
     return re.sub(r"\(.*", "", name).replace("void ", "").strip()
 
 
