@@ -279,6 +279,17 @@ def scc_measure(ctx):
         out[name] = {"atoms": int(s.n_atoms), "N": int(s.n), "shifts": int(len(z)), "iterations": r["iterations"],
                      "residual": r["residual"], "seconds": dt, "seconds_per_iteration": dt / r["iterations"],
                      "converged": r["status"] == 0}
+    # the oracle's loop (dense LU per shift), 1 thread, on the small box
+    from threadpoolctl import threadpool_limits
+
+    from oracle import csc as ocsc
+    gamma = ocsc.gamma_matrix(small, hubbard_u(small))
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        _, _, _, it_or, _ = ocsc.scc(small, S, H0, gamma, z, w, beta=0.2, tol=1e-9, max_iter=200, history=4)
+        t_or = time.perf_counter() - t0
+    out["cpu_oracle_water8"] = {"kind": "oracle", "cores": 1, "seconds": t_or, "iterations": it_or,
+                                "seconds_per_iteration": t_or / max(it_or, 1)}
     return out
 
 
@@ -309,6 +320,16 @@ def charge_vjp_measure(ctx):
     torch.cuda.synchronize()
     out["band_energy_vjp_seconds"] = time.perf_counter() - t0
     out["rel_diff"] = float(max(np.abs(dH - eH).max() / np.abs(eH).max(), np.abs(dS - eS).max() / np.abs(eS).max()))
+    # the oracle's dense form of the same gradient, 1 thread
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ased as oased, green as ogreen
+    S, H, _ = oased.dense_pair(s)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        ogreen.charge_grad_dense(H, S, z, w * z.real, orbs, np.ones(s.n))
+        out["cpu_oracle_seconds"] = time.perf_counter() - t0
+    out["cpu_oracle"] = "oracle/green.py charge_grad_dense (dense inverses per shift), 1 thread"
     return out
 
 
