@@ -389,3 +389,9 @@ def test_chebyshev_column_blocks(ctx, block):
         resp = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, inner_method=2, cheb_block=block,
                          carry="projected", proj=rhs[:, None])
         assert rel(resp.G_proj[:, :, 0], X[:, np.arange(len(rhs)), rhs]) < 1e-10
+        # complex64 products: the same arithmetic per column, blocked or not
+        resm = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-6, inner_method=2, cheb_block=block,
+                         precision="mixed")
+        refm = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-6, inner_method=2, precision="mixed")
+        assert rel(resm.G_cols, refm.G_cols) < 1e-12
+        assert rel(resm.G_cols, X) < 1e-3
