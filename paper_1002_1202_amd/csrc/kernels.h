@@ -133,10 +133,10 @@ __device__ inline void st_cpx(cpx<T> v, cpx<T> *p) {
 // gathered diagonal block), Sx = the gathered product.  MODE 0: the first
 // step, whose gathered vector is r and y_1 = r / theta, y_0 = 0; MODE 1:
 // y_{k-1} = y_1 = r / theta is formed from r; MODE 2: y_{k-1} is read.
-// Returns |res|^2.
+// Returns |res|^2; with dacc, also adds y_{k+1} r (unconjugated, FP64) to it.
 template <typename T, int MODE, bool NT>
 __device__ inline double cheb_update(cpx<T> own, cpx<T> Sx, const cpx<T> *__restrict__ r, cpx<T> *__restrict__ yio,
-                                     size_t e, T inv_theta, T c1, T c2) {
+                                     size_t e, T inv_theta, T c1, T c2, c128 *dacc = nullptr) {
     cpx<T> yk, rv, yprev, Sy = Sx;
     if constexpr (MODE == 0) {
         rv = own;
@@ -150,7 +150,9 @@ __device__ inline double cheb_update(cpx<T> own, cpx<T> Sx, const cpx<T> *__rest
         else yprev = ld_cpx<T, NT>(yio + e);
     }
     const cpx<T> res = rv - Sy;
-    st_cpx<T, NT>(yk + c1 * (yk - yprev) + c2 * res, yio + e);
+    const cpx<T> ynew = yk + c1 * (yk - yprev) + c2 * res;
+    st_cpx<T, NT>(ynew, yio + e);
+    if (dacc) *dacc = *dacc + ccast<double>(ynew) * ccast<double>(rv);
     return static_cast<double>(res.re) * res.re + static_cast<double>(res.im) * res.im;
 }
 

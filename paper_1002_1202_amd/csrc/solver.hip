@@ -1509,11 +1509,12 @@ template <typename T> class TileSolver {
         k_update_r<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_alpha.get(), t_.q.get(),
                                          t_.r.get(), t_.res.get(), t_.d.get(), t_.part_d.get(), cheb_ok_ ? 0 : 1);
         k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 0, inner_tol_, cs);
-        inner_solve_cheb(o, cs, rp);
-        k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), rp, t_.r.get(),
-                                        t_.part_c.get());
-        k_post<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.G, n, 0, t_.part_c.get(), o.tol, cs, ss, t_.h.get(),
-                                          t_.dh.get(), t_.Mu + t_.srow);
+        const bool fused = inner_solve_cheb(o, cs, rp, t_.part_c.get());
+        if (!fused)
+            k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), rp, t_.r.get(),
+                                            t_.part_c.get());
+        k_post<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, fused ? td.Gs : td.G, n, 0, t_.part_c.get(), o.tol, cs, ss,
+                                          t_.h.get(), t_.dh.get(), t_.Mu + t_.srow);
         k_p_update<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, 0, cs, rp, t_.r.get(), t_.p.get(), t_.P.get(),
                                          t_.ldk, nullptr);
         GSC_HIP(hipGetLastError());
@@ -1571,14 +1572,18 @@ template <typename T> class TileSolver {
                                              cheb_ok_ ? 0 : 1);
             prof_.end(st_);
             k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 0, inner_tol, cs);
-            inner_solve(o, cs, rp_next);
-            prof_.begin(st_, KP_RHO_DOT, 0.0);
-            k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), rp_next,
-                                            t_.r.get(), t_.part_c.get());
-            prof_.end(st_);
+            // rho = r'^T r comes out of the Chebyshev iteration's last step
+            // (partials over its row groups), else from its own pass
+            const bool fused = inner_solve(o, cs, rp_next, t_.part_c.get());
+            if (!fused) {
+                prof_.begin(st_, KP_RHO_DOT, 0.0);
+                k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), rp_next,
+                                                t_.r.get(), t_.part_c.get());
+                prof_.end(st_);
+            }
             prof_.begin(st_, KP_POST, 0.0);
-            k_post<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.G, n, full_ ? 1 : 0, t_.part_c.get(), o.tol, cs,
-                                              ss, t_.h.get(), t_.dh.get(), t_.Mu + t_.srow);
+            k_post<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, fused ? td.Gs : td.G, n, full_ ? 1 : 0, t_.part_c.get(),
+                                              o.tol, cs, ss, t_.h.get(), t_.dh.get(), t_.Mu + t_.srow);
             prof_.end(st_);
             GSC_HIP(hipGetLastError());
             const Status s = check_status(true);
@@ -1857,9 +1862,12 @@ template <typename T> class TileSolver {
         return s;
     }
 
-    void inner_solve(const gsc_opts &o, ColState cs, cpx<T> *y) {
-        if (cheb_ok_) inner_solve_cheb(o, cs, y);
-        else inner_solve_cg(o, cs, y);
+    // S y = r; with dot_part, returns true when the partials of y^T r over
+    // the product kernels' row groups (td.Gs) were left there as well
+    bool inner_solve(const gsc_opts &o, ColState cs, cpx<T> *y, c128 *dot_part = nullptr) {
+        if (cheb_ok_) return inner_solve_cheb(o, cs, y, dot_part);
+        inner_solve_cg(o, cs, y);
+        return false;
     }
 
     // Interval for the Chebyshev iteration from the Ritz values of the first
@@ -1899,8 +1907,10 @@ template <typename T> class TileSolver {
     // check at tol that flags columns still above it.  Three-term form:
     // step k reads y_k (gathered) and y_{k-1} and writes y_{k+1} over y_{k-1},
     // so two buffers alternate.
-    void inner_solve_cheb(const gsc_opts &o, ColState cs, cpx<T> *ytarget) {
+    bool inner_solve_cheb(const gsc_opts &o, ColState cs, cpx<T> *ytarget, c128 *dot_part = nullptr) {
         (void)o;
+        // the fused y^T r needs the row layout (td.variant 0)
+        const bool dot = dot_part != nullptr && td_variant_row();
         auto &td = t_.td;
         const T *Sv = sval();
         const double sigma = cheb_theta_ / cheb_delta_;
@@ -1909,7 +1919,7 @@ template <typename T> class TileSolver {
         buf[K % 2] = ytarget;
         buf[(K + 1) % 2] = t_.w.get();
         double rho_prev = 1.0 / sigma;
-        auto step = [&](int kk, const int *skip, int c0, int w) {
+        auto step = [&](int kk, const int *skip, int c0, int w, int dot_mode) {
             const double rho = 1.0 / (2.0 * sigma - rho_prev);
             const double c1 = rho * rho_prev, c2 = 2.0 * rho / cheb_delta_;
             const int mode = kk == 1 ? 0 : kk == 2 ? 1 : 2;
@@ -1918,7 +1928,8 @@ template <typename T> class TileSolver {
                                   1.0 / cheb_theta_, c1, c2, t_.part_d.get());
             else
                 launch_cheb_step<T>(st_, pr_, td, mode, c0, w, Sv, buf[kk % 2], t_.r.get(), buf[(kk + 1) % 2],
-                                    skip, 1.0 / cheb_theta_, c1, c2, t_.part_d.get());
+                                    skip, 1.0 / cheb_theta_, c1, c2, t_.part_d.get(), dot ? dot_part : nullptr,
+                                    dot ? dot_mode : 0);
             rho_prev = rho;
         };
         // the K - 1 steps of each column block run back to back (columns are
@@ -1931,20 +1942,23 @@ template <typename T> class TileSolver {
         prof_.begin_group(st_, KP_CHEB);
         for (int c0 = 0; c0 < td.Rp; c0 += cb) {
             rho_prev = 1.0 / sigma;
-            for (int k = 1; k < K; ++k, ++launches) step(k, t_.c_done.get(), c0, std::min(cb, td.Rp - c0));
+            for (int k = 1; k < K; ++k, ++launches)
+                step(k, t_.c_done.get(), c0, std::min(cb, td.Rp - c0), k == K - 1 ? 1 : 0);
         }
         prof_.end_group(st_, launches, bytes);
         k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_ / cheb_rho_, 0, cs);
         // extra steps for the columns that failed the check (bytes counted
         // from the check's outcome are not known here: counted as zero)
         prof_.begin_group(st_, KP_CHEB);
-        step(K, t_.c_inner_done.get(), 0, td.Rp);
-        step(K + 1, t_.c_inner_done.get(), 0, td.Rp);
+        step(K, t_.c_inner_done.get(), 0, td.Rp, 0);
+        step(K + 1, t_.c_inner_done.get(), 0, td.Rp, 2);
         prof_.end_group(st_, 2, 0.0);
         k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_, 1, cs);
         GSC_HIP(hipGetLastError());
         inner_total_ += K - 1;
+        return dot;
     }
+    bool td_variant_row() const { return t_.td.variant == 0; }
 
     void inner_solve_cg(const gsc_opts &o, ColState cs, cpx<T> *y) {
         auto &td = t_.td;

@@ -20,7 +20,7 @@ void launch_spmm_S(hipStream_t st, const Pair &pr, const TileDims &td, const T *
 template <typename T>
 void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, int mode, int col0, int ncols, const T *Sv,
                       const cpx<T> *y, const cpx<T> *r, cpx<T> *yio, const int *skip, double inv_theta,
-                      double c1, double c2, double *partial);
+                      double c1, double c2, double *partial, c128 *dpart = nullptr, int dot_mode = 0);
 
 template <typename T>
 void launch_cheb_split(hipStream_t st, const Pair &pr, const TileDims &td, int mode, const T *Sv, const cpx<T> *y,

@@ -323,13 +323,16 @@ __global__ __launch_bounds__(kBlock) void k_spmm_S_cl(
 // form (see cheb_update): one gathered vector (y_k, or r in the first
 // step), r and y_{k-1} streamed, y_{k+1} written over y_{k-1}, and a
 // partial ||r - S y_k||^2.  A launch covers the columns [col0, col0 +
-// 64 gridDim.x) of the Rp-wide tile.
-template <typename T, int B, int MODE, bool NT>
+// 64 gridDim.x) of the Rp-wide tile.  DOT: the step is a column's last, and
+// the partial of y_{k+1}^T r (unconjugated: the next rho of the outer
+// iteration, eq. CGp:p) goes to dpart as well, for every column
+// (dot_active_only = 0) or only for the columns that take this step.
+template <typename T, int B, int MODE, bool NT, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(
     int nb, int Rp, int col0, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
     const T *__restrict__ Sv, const cpx<T> *__restrict__ y, const cpx<T> *__restrict__ r,
     cpx<T> *__restrict__ yio, const int *__restrict__ skip, T inv_theta, T c1, T c2,
-    double *__restrict__ partial) {
+    double *__restrict__ partial, c128 *__restrict__ dpart, int dot_active_only) {
     int cx, g;
     xcd_remap_chunks(cx, g);
     const int lane = threadIdx.x & 63;
@@ -337,6 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
     const int col = col0 + cx * 64 + lane;
     const bool act = !skip[col];
     double acc2 = 0.0;
+    c128 dacc{0.0, 0.0};
     // rows of this wave: every row group takes one row per wave per step, so
     // the groups advance together (step i covers rows [i*4*Gs, (i+1)*4*Gs))
     // and the rows in flight on an XCD stay within one window, however many
@@ -380,12 +384,24 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
 #pragma unroll
             for (int a = 0; a < B; ++a)
                 acc2 += cheb_update<T, MODE, NT>(own[a], aS[a], r, yio, static_cast<size_t>(I * B + a) * Rp + col,
-                                                 inv_theta, c1, c2);
+                                                 inv_theta, c1, c2, DOT ? &dacc : nullptr);
         }
     }
     __shared__ double red[kWavesPerBlock][64];
     red[wv][lane] = acc2;
-    __syncthreads();
+    if constexpr (DOT) {
+        __shared__ c128 redc[kWavesPerBlock][64];
+        redc[wv][lane] = dacc;
+        __syncthreads();
+        if (threadIdx.x < 64 && (act || !dot_active_only)) {
+            c128 t = redc[0][lane];
+#pragma unroll
+            for (int k = 1; k < kWavesPerBlock; ++k) t = t + redc[k][lane];
+            dpart[static_cast<size_t>(g) * Rp + col] = t;
+        }
+    } else {
+        __syncthreads();
+    }
     if (threadIdx.x < 64) {
         double t = red[0][lane];
 #pragma unroll
@@ -397,10 +413,11 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(
 template <typename T>
 void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, int mode, int col0, int ncols,
                       const T *Sv, const cpx<T> *y, const cpx<T> *r, cpx<T> *yio, const int *skip,
-                      double inv_theta, double c1, double c2, double *partial) {
+                      double inv_theta, double c1, double c2, double *partial, c128 *dpart, int dot_mode) {
     GSC_REQUIRE(col0 % 64 == 0 && ncols % 64 == 0 && ncols > 0 && col0 + ncols <= td.Rp,
                 "Chebyshev column block outside the tile");
     GSC_REQUIRE(td.variant == 0 || (col0 == 0 && ncols == td.Rp), "column blocks need the row layout");
+    GSC_REQUIRE(dot_mode == 0 || (td.variant == 0 && dpart != nullptr), "the fused dot needs the row layout");
     if (td.variant == 2) {
         launch_cheb_slab<T>(st, pr, td, mode, Sv, y, r, yio, skip, inv_theta, c1, c2, partial);
         return;
@@ -412,26 +429,29 @@ void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, int mo
     // the fused step uses the row layout (one block row per wave and step)
     dim3 grid(ncols / 64, td.Gs), block(kBlock);
     const T it = static_cast<T>(inv_theta), a = static_cast<T>(c1), b = static_cast<T>(c2);
-#define GSC_CHEB(BB, M, N)                                                                                      \
-    k_cheb_step<T, BB, M, N><<<grid, block, 0, st>>>(td.nb, td.Rp, col0, pr.rowptr.get(), pr.colidx.get(), Sv, \
-                                                     y, r, yio, skip, it, a, b, partial)
+#define GSC_CHEB_D(BB, M, N, D)                                                                                   \
+    k_cheb_step<T, BB, M, N, D><<<grid, block, 0, st>>>(td.nb, td.Rp, col0, pr.rowptr.get(), pr.colidx.get(), Sv, \
+                                                        y, r, yio, skip, it, a, b, partial, dpart, dot_mode == 2)
+#define GSC_CHEB(BB, M, N) \
+    if (dot_mode) GSC_CHEB_D(BB, M, N, true); else GSC_CHEB_D(BB, M, N, false);
 #define GSC_CHEB_N(BB, M) \
-    if (td.nt) GSC_CHEB(BB, M, true); else GSC_CHEB(BB, M, false);
+    if (td.nt) { GSC_CHEB(BB, M, true) } else { GSC_CHEB(BB, M, false) }
 #define GSC_CHEB_B(BB) \
     if (mode == 0) { GSC_CHEB_N(BB, 0) } else if (mode == 1) { GSC_CHEB_N(BB, 1) } else { GSC_CHEB_N(BB, 2) }
     if (pr.B == 4) { GSC_CHEB_B(4) } else { GSC_CHEB_B(6) }
 #undef GSC_CHEB_B
 #undef GSC_CHEB_N
 #undef GSC_CHEB
+#undef GSC_CHEB_D
     GSC_HIP(hipGetLastError());
 }
 
 template void launch_cheb_step<double>(hipStream_t, const Pair &, const TileDims &, int, int, int, const double *,
                                        const c128 *, const c128 *, c128 *, const int *, double, double, double,
-                                       double *);
+                                       double *, c128 *, int);
 template void launch_cheb_step<float>(hipStream_t, const Pair &, const TileDims &, int, int, int, const float *,
                                       const c64 *, const c64 *, c64 *, const int *, double, double, double,
-                                      double *);
+                                      double *, c128 *, int);
 
 // ------------------------------------------------------------------ launchers
 // Row-group geometry of the product kernels.  Every reduction of their
