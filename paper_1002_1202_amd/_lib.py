@@ -59,6 +59,7 @@ SIGNATURES = {
     "gsc_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, _VP]),
     "gsc_set_stream": (C.c_int, [_VP, _VP]),
     "gsc_destroy": (None, [_VP]),
+    "gsc_release_cache": (C.c_int, []),
     "gsc_last_error": (C.c_char_p, []),
     "gsc_version": (C.c_char_p, []),
     "gsc_pair_create": (C.c_int, [_VP, C.c_int, C.c_int64, _I64P, _I32P, _VP, _VP, C.c_int,

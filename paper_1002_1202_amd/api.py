@@ -78,6 +78,11 @@ def profile_enable(ctx: Context, on: bool = True, only: str | None = None):
         L.check(ctx.lib.gsc_profile_select(ctx.h, only.encode() if only else None))
 
 
+def release_cache(ctx: Context) -> None:
+    """Hand the library's cached device blocks back to the runtime."""
+    L.check(ctx.lib.gsc_release_cache())
+
+
 def profile_read(ctx: Context) -> dict:
     """{kernel: (total_ms, launches, algorithmic_bytes)} since profile_enable."""
     out = {}

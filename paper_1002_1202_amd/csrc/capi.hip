@@ -182,7 +182,17 @@ gsc_status gsc_set_stream(gsc_ctx *ctx, void *stream) {
     });
 }
 
-void gsc_destroy(gsc_ctx *ctx) { delete ctx; }
+void gsc_destroy(gsc_ctx *ctx) {
+    delete ctx;
+    dev_cache_release();
+}
+
+gsc_status gsc_release_cache(void) {
+    return guarded([&] {
+        dev_cache_release();
+        return GSC_OK;
+    });
+}
 
 gsc_status gsc_pair_create(gsc_ctx *ctx, int block, int64_t nbrows, const int64_t *rowptr,
                            const int32_t *colidx, const double *Hval, const double *Sval, int mem,
@@ -448,8 +458,7 @@ gsc_status gsc_charge_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, const 
         GSC_HIP(hipMemcpyAsync(dz.get(), z, nshift * sizeof(c128), hipMemcpyHostToDevice, st));
         GSC_HIP(hipMemcpyAsync(dw.get(), w, nshift * sizeof(double), hipMemcpyHostToDevice, st));
         // orbitals per tile: two [K][R][N] complex solution sets in 40 % of free memory
-        size_t freeb = 0, totalb = 0;
-        GSC_HIP(hipMemGetInfo(&freeb, &totalb));
+        const size_t freeb = dev_usable_bytes();
         const double per = 2.0 * nshift * static_cast<double>(p.n) * sizeof(c128) + 16.0 * p.n * sizeof(c128);
         int Rt = o.rhs_tile > 0 ? o.rhs_tile : static_cast<int>(0.4 * static_cast<double>(freeb) / per);
         Rt = std::max(1, std::min(Rt, norb));

@@ -64,6 +64,22 @@ template <typename To, typename From> __host__ __device__ inline cpx<To> ccast(c
 }
 
 // ------------------------------------------------------------------ device memory
+// ------------------------------------------------------------------ device memory
+// Every library temporary comes from dev_alloc.  Blocks of at least 64 MiB
+// are kept after dev_free (per device, up to a third of its memory) and
+// handed to later requests of at most their size and at least half of it:
+// freshly mapped device memory is cleared by the driver, which for the tens
+// of GB of a full-carry solve costs about a second whenever the sizes of
+// consecutive calls differ.  A block is reused only by work enqueued after
+// its release; the entry points release temporaries after their stream
+// work (or on the stream the later work runs on).  Cached blocks hold no
+// data the caller can see.
+void *dev_alloc(size_t bytes);
+void dev_free(void *p);
+size_t dev_cache_bytes(int device);   // bytes cached for this device
+size_t dev_usable_bytes();            // free device memory plus this device's cache
+void dev_cache_release();             // hand every cached block back
+
 template <typename T> struct DevBuf {
     T *ptr = nullptr;
     size_t n = 0;
@@ -79,11 +95,11 @@ template <typename T> struct DevBuf {
     ~DevBuf() { release(); }
     void alloc(size_t count) {
         release();
+        if (count) ptr = static_cast<T *>(dev_alloc(count * sizeof(T)));
         n = count;
-        if (count) GSC_HIP(hipMalloc(&ptr, count * sizeof(T)));
     }
     void release() {
-        if (ptr) (void)hipFree(ptr);
+        if (ptr) dev_free(ptr);
         ptr = nullptr;
         n = 0;
     }

@@ -2103,15 +2103,13 @@ gsc_status solve_typed(Ctx &ctx, SolveRequest &req) {
     // tile width: all rhs if memory allows
     int Rt = o.rhs_tile > 0 ? o.rhs_tile : req.R;
     if (full && o.rhs_tile <= 0) {
-        size_t freeb = 0, totalb = 0;
-        GSC_HIP(hipMemGetInfo(&freeb, &totalb));
+        const size_t freeb = dev_usable_bytes();
         const double per_col = 2.0 * req.K * N * sizeof(cpx<T>) + 16.0 * N * sizeof(cpx<T>);
         const int fit = static_cast<int>(0.8 * static_cast<double>(freeb) / per_col);
         Rt = std::max(1, std::min(Rt, fit));
     }
     if (!full && o.rhs_tile <= 0) {
-        size_t freeb = 0, totalb = 0;
-        GSC_HIP(hipMemGetInfo(&freeb, &totalb));
+        const size_t freeb = dev_usable_bytes();
         const int M = (req.proj ? req.proj->M : 0) + 1;
         const double per_col = 10.0 * N * sizeof(cpx<T>) + static_cast<double>(req.K) * (M * 2.0 * 16 + 256.0);
         const int fit = static_cast<int>(0.6 * static_cast<double>(freeb) / per_col);
@@ -2353,8 +2351,7 @@ gsc_status lanczos_typed(Ctx &ctx, LanczosRequest &req) {
     const double inner_tol = default_inner_tol<T>(o);
     int Pt = o.rhs_tile > 0 ? o.rhs_tile : req.P;
     if (o.rhs_tile <= 0) {
-        size_t freeb = 0, totalb = 0;
-        GSC_HIP(hipMemGetInfo(&freeb, &totalb));
+        const size_t freeb = dev_usable_bytes();
         // per column: ~12 vectors plus coefficient rows of two processes
         const double per_col = 12.0 * N * sizeof(cpx<T>) + 4.0 * req.m_max * sizeof(double) + 32.0 * req.K;
         const int fit = static_cast<int>(0.6 * static_cast<double>(freeb) / per_col);
