@@ -70,10 +70,9 @@ template <typename To, typename From> __host__ __device__ inline cpx<To> ccast(c
 // handed to later requests of at most their size and at least half of it:
 // freshly mapped device memory is cleared by the driver, which for the tens
 // of GB of a full-carry solve costs about a second whenever the sizes of
-// consecutive calls differ.  A block is reused only by work enqueued after
-// its release; the entry points release temporaries after their stream
-// work (or on the stream the later work runs on).  Cached blocks hold no
-// data the caller can see.
+// consecutive calls differ.  Like hipFree, dev_free of such a block waits
+// for the device to go idle before the block can be handed out again.
+// Cached blocks hold no data the caller can see.
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
 size_t dev_cache_bytes(int device);   // bytes cached for this device

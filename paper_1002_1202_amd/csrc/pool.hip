@@ -81,24 +81,39 @@ void *dev_alloc(size_t bytes) {
 void dev_free(void *p) {
     if (p == nullptr) return;
     Pool &P = pool();
+    size_t sz = 0;
+    int dev = -1;
     {
         std::lock_guard<std::mutex> lk(P.m);
         auto it = P.live.find(p);
         if (it != P.live.end()) {
-            const size_t sz = it->second.first;
-            const int dev = it->second.second;
+            sz = it->second.first;
+            dev = it->second.second;
             P.live.erase(it);
-            auto lim = P.limit.find(dev);
-            if (lim == P.limit.end()) {
+            if (P.limit.find(dev) == P.limit.end()) {
                 size_t freeb = 0, totalb = 0;
                 int cur = -1;
                 (void)hipGetDevice(&cur);
                 (void)hipSetDevice(dev);
                 if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) totalb = 0;
                 if (cur >= 0) (void)hipSetDevice(cur);
-                lim = P.limit.emplace(dev, totalb / 3).first;
+                P.limit.emplace(dev, totalb / 3);
             }
-            if (P.cached[dev] + sz <= lim->second) {
+            if (P.cached[dev] + sz > P.limit[dev]) dev = -1;
+        }
+    }
+    if (dev >= 0) {
+        // hipFree waits for the device to go idle; a cached block has to as
+        // well, or a call on another stream could receive it while kernels
+        // still use it (the wait runs outside the lock)
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (cur != dev) (void)hipSetDevice(dev);
+        const bool idle = hipDeviceSynchronize() == hipSuccess;
+        if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+        if (idle) {
+            std::lock_guard<std::mutex> lk(P.m);
+            if (P.cached[dev] + sz <= P.limit[dev]) {
                 P.free.insert({{dev, sz}, p});
                 P.cached[dev] += sz;
                 return;
