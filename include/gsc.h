@@ -79,8 +79,9 @@ typedef struct {
                               replaces seed switching by a collinear restart   */
     int seed_index;        /* [-1] initial seed shift; -1 = the shift whose
                               real part is nearest the middle of the grid     */
-    int fuse_steps;        /* [0 = auto] number m of shift-update steps applied
-                              per pass over the shifted vectors (full carry)   */
+    int fuse_steps;        /* [0 = auto = 16] number m of shift-update steps
+                              applied per pass over the shifted vectors (full
+                              carry), 1..16                                    */
     int rhs_tile;          /* [0 = auto] right-hand sides per device tile      */
     int recheck;           /* [0] 1: FP64 true residual of every (k, rhs) into
                               gsc_stats.res_true (full carry only)             */
@@ -112,7 +113,16 @@ typedef struct {
                               time; auto sizes the block so that the step's
                               three vectors fit the 256 MB infinity cache
                               (no blocking when the tile already fits)        */
-    int reserved[3];
+    int inner_relax;       /* [0] 1: relaxed inner tolerance (Chebyshev inner
+                              solves outside batched graphs): each outer
+                              iteration solves S r' = r to inner_tol divided
+                              by the largest residual among the shifts still
+                              above tol (at most 1e-6, at least inner_tol),
+                              so the inner error that reaches every
+                              unconverged shift stays at inner_tol relative
+                              to ||b||.  0 keeps the fixed inner_tol of the
+                              method.                                         */
+    int reserved[2];
 } gsc_opts;
 
 /* Statistics.  The three arrays are caller-owned HOST arrays of

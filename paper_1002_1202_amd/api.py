@@ -197,7 +197,8 @@ def spmm(ctx: Context, pair: Pair, X, alpha_S):
 
 def make_opts(tol=1e-10, max_iter=5000, inner_tol=0.0, inner_max_iter=200, precision="fp64",
               carry="full", seed_index=-1, fuse_steps=0, rhs_tile=0, recheck=False,
-              spmm_kernel=0, inner_method=0, graph_iters=0, stream_hint=0, cheb_block=0) -> L.Opts:
+              spmm_kernel=0, inner_method=0, graph_iters=0, stream_hint=0, cheb_block=0,
+              inner_relax=False) -> L.Opts:
     o = L.Opts()
     L.load().gsc_opts_default(C.byref(o))
     o.tol, o.max_iter, o.inner_tol, o.inner_max_iter = tol, max_iter, inner_tol, inner_max_iter
@@ -209,6 +210,7 @@ def make_opts(tol=1e-10, max_iter=5000, inner_tol=0.0, inner_max_iter=200, preci
     o.graph_iters = graph_iters
     o.stream_hint = stream_hint
     o.cheb_block = cheb_block
+    o.inner_relax = int(inner_relax)
     return o
 
 

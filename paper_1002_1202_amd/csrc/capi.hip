@@ -120,6 +120,7 @@ void validate_opts(const gsc_opts &o) {
     GSC_REQUIRE(o.spmm_kernel >= 0 && o.spmm_kernel <= 4, "spmm_kernel must be 0 .. 4");
     GSC_REQUIRE(o.stream_hint >= 0 && o.stream_hint <= 2, "stream_hint must be 0, 1 or 2");
     GSC_REQUIRE(o.cheb_block >= 0 && o.cheb_block % 64 == 0, "cheb_block must be 0 or a multiple of 64");
+    GSC_REQUIRE(o.inner_relax == 0 || o.inner_relax == 1, "inner_relax must be 0 or 1");
     GSC_REQUIRE(o.inner_method >= 0 && o.inner_method <= 2, "inner_method must be 0, 1 or 2");
 }
 

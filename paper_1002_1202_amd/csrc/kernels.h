@@ -33,6 +33,7 @@ struct ColState {
     long long *act_hist;      // [max_iter] active (shift, column) pairs per iteration
     long long *col_hist;      // [max_iter] unfinished columns per iteration
     double *cg_ha, *cg_hb;    // [Rp][kHist] CG step sizes and beta of a recorded solve (or null)
+    double *wres;             // largest residual over the column's unconverged shifts (-1: none)
 };
 
 // (shift, column) state.

@@ -8,6 +8,7 @@ struct Status {
     int inner_pending;     // columns whose inner S-solve has not converged
     int switched;          // columns that switched seed (or restarted) this iteration
     int flags;             // OR of FLAG_* over columns
+    double worst_res;      // largest shifted residual still above tol, over columns (-1: none)
 };
 
 // Projections carried by the projected mode: M unit vectors c_m = e_i per

@@ -89,6 +89,7 @@ __global__ void k_init_cols(int R, int Rp, int seed0, ColState cs) {
     cs.zres[c] = 0;
     cs.inner_done[c] = 1;
     cs.inner_count[c] = 0;
+    cs.wres[c] = 1.0;
 }
 
 __global__ void k_init_shifts(int K, int R, int Rp, ShiftState ss) {
@@ -348,6 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_post(int K, int Rp, int G, int n, in
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        cs.wres[c] = s_res[0];
         const c128 rho = cs.rho[c];
         const c128 beta = cdiv(rho_new, rho);
         cs.alpha_prev[c] = cs.alpha[c];
@@ -540,15 +542,18 @@ __global__ void k_copy_vec(size_t n, const cpx<T> *a, cpx<T> *b) {
 
 __global__ void k_status(int Rp, ColState cs, Status *st) {
     __shared__ int a[kBlock], b[kBlock], s[kBlock], f[kBlock];
+    __shared__ double wr[kBlock];
     int na = 0, nb = 0, ns = 0, fl = 0;
+    double w = -1.0;
     for (int c = threadIdx.x; c < Rp; c += kBlock) {
         const int done = cs.done[c];
         na += !done;
         nb += (!done && !cs.inner_done[c]);
         ns += (!done && cs.sw[c] != 0);
         fl |= cs.flags[c];
+        if (!done) w = fmax(w, cs.wres[c]);
     }
-    a[threadIdx.x] = na; b[threadIdx.x] = nb; s[threadIdx.x] = ns; f[threadIdx.x] = fl;
+    a[threadIdx.x] = na; b[threadIdx.x] = nb; s[threadIdx.x] = ns; f[threadIdx.x] = fl; wr[threadIdx.x] = w;
     __syncthreads();
     for (int k = kBlock / 2; k > 0; k >>= 1) {
         if (threadIdx.x < k) {
@@ -556,6 +561,7 @@ __global__ void k_status(int Rp, ColState cs, Status *st) {
             b[threadIdx.x] += b[threadIdx.x + k];
             s[threadIdx.x] += s[threadIdx.x + k];
             f[threadIdx.x] |= f[threadIdx.x + k];
+            wr[threadIdx.x] = fmax(wr[threadIdx.x], wr[threadIdx.x + k]);
         }
         __syncthreads();
     }
@@ -564,6 +570,7 @@ __global__ void k_status(int Rp, ColState cs, Status *st) {
         st->inner_pending = b[0];
         st->switched = s[0];
         st->flags = f[0];
+        st->worst_res = wr[0];
     }
 }
 
@@ -1285,7 +1292,7 @@ template <typename T> struct Tile {
     size_t ldk = 0;
     // column state
     DevBuf<c128> c_rho, c_alpha, c_alpha_prev, c_beta_prev, c_swc, c_swcm;
-    DevBuf<double> c_bnorm, c_rnorm2, c_rr, c_rr_stop, c_cg_a, c_cg_b;
+    DevBuf<double> c_bnorm, c_rnorm2, c_rr, c_rr_stop, c_cg_a, c_cg_b, c_wres;
     DevBuf<int> c_seed, c_done, c_inner_done, c_cg_first, c_sw, c_applied, c_flags, c_zres, c_inner_count,
         c_iters;
     DevBuf<long long> c_shift_iters, c_inner_total, act_hist, col_hist;
@@ -1313,7 +1320,7 @@ template <typename T> struct Tile {
         c.applied = c_applied.get(); c.flags = c_flags.get(); c.zres = c_zres.get();
         c.inner_count = c_inner_count.get(); c.shift_iters = c_shift_iters.get(); c.iters = c_iters.get();
         c.inner_total = c_inner_total.get(); c.act_hist = act_hist.get(); c.col_hist = col_hist.get();
-        c.cg_ha = cg_ha.get(); c.cg_hb = cg_hb.get();
+        c.cg_ha = cg_ha.get(); c.cg_hb = cg_hb.get(); c.wres = c_wres.get();
         return c;
     }
     ShiftState shifts(const c128 *z) {
@@ -1395,6 +1402,7 @@ template <typename T> class TileSolver {
         t_.c_sw.alloc(Rp); t_.c_applied.alloc(Rp); t_.c_flags.alloc(Rp); t_.c_zres.alloc(Rp);
         t_.c_inner_count.alloc(Rp); t_.c_iters.alloc(Rp); t_.c_shift_iters.alloc(Rp);
         t_.c_inner_total.alloc(Rp);
+        t_.c_wres.alloc(Rp);
         t_.cg_ha.alloc(Rp * kHist);
         t_.cg_hb.alloc(Rp * kHist);
         const size_t KR = static_cast<size_t>(td.K) * Rp;
@@ -1476,6 +1484,7 @@ template <typename T> class TileSolver {
                                          t_.d.get(), t_.part_d.get());
         k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 1, inner_tol, cs);
         inner_tol_ = inner_tol;
+        inner_tol_base_ = inner_tol;
         inner_solve_cg(o, cs, t_.ring.get());
         if (full_) {
             k_ring_transpose<T><<<dim3(td.Rp / 64, div_up(td.N, 32)), kBlock, 0, st_>>>(td.N, td.Rp, t_.ring.get(),
@@ -1587,6 +1596,7 @@ template <typename T> class TileSolver {
             prof_.end(st_);
             GSC_HIP(hipGetLastError());
             const Status s = check_status(true);
+            if (o.inner_relax) relax_inner(s.worst_res);
             if (full_ && s.switched > 0) {
                 flush(cs, ss, n0, n + 1, 1, s.switched);
                 k_mark_applied<<<cb, 256, 0, st_>>>(td.Rp, n + 1, cs);
@@ -1892,12 +1902,33 @@ template <typename T> class TileSolver {
         cheb_delta_ = 0.5 * (b - a);
         const double kappa = b / a;
         cheb_rho_ = (std::sqrt(kappa) - 1.0) / (std::sqrt(kappa) + 1.0);
-        const double lr = std::log(1.0 / std::max(cheb_rho_, 1e-300));
-        cheb_steps_ = std::max(2, static_cast<int>(std::ceil(std::log(2.0 / tol_in) / lr)));
-        cheb_steps_ = std::min(cheb_steps_, o.inner_max_iter);
+        cheb_max_ = o.inner_max_iter;
+        cheb_steps_ = cheb_steps_for(tol_in);
         cheb_ok_ = true;
         cheb_lo_ = h[0];
         cheb_hi_ = h[1];
+    }
+
+    // steps K of the Chebyshev iteration for a relative residual tol: the
+    // error bound 2 rho^K of the interval
+    int cheb_steps_for(double tol) const {
+        const double lr = std::log(1.0 / std::max(cheb_rho_, 1e-300));
+        const int k = std::max(2, static_cast<int>(std::ceil(std::log(2.0 / tol) / lr)));
+        return std::min(k, cheb_max_);
+    }
+
+    // Relaxed inner tolerance (option inner_relax).  An error e in r' = S^-1 r
+    // enters shift k's iterate as e / pi^k, i.e. scaled by that shift's
+    // residual ||r|| / (|pi^k| ||b||); a relative inner tolerance of
+    // tol_in / (largest residual still above tol) therefore keeps what every
+    // unconverged shift receives at tol_in relative to ||b||, as in its first
+    // iteration.  Capped at kRelaxCap; the fixed tolerance is the floor.
+    void relax_inner(double worst) {
+        if (!cheb_ok_ || !(inner_tol_base_ > 0.0)) return;
+        double t = worst > 0.0 ? inner_tol_base_ / worst : inner_tol_base_;
+        t = std::max(std::min(t, kRelaxCap), inner_tol_base_);
+        inner_tol_ = t;
+        cheb_steps_ = cheb_steps_for(t);
     }
 
     // Chebyshev iteration for S y = r (r in t_.r), y_K written to `ytarget`,
@@ -2055,7 +2086,9 @@ template <typename T> class TileSolver {
     double inner_tol_ = 1e-12;
     bool cheb_ok_ = false;
     double cheb_theta_ = 1.0, cheb_delta_ = 0.5, cheb_rho_ = 0.5, cheb_lo_ = 0.0, cheb_hi_ = 0.0;
-    int cheb_steps_ = 0;
+    int cheb_steps_ = 0, cheb_max_ = 200;
+    double inner_tol_base_ = 0.0;     // the fixed inner tolerance of the solve
+    static constexpr double kRelaxCap = 1e-6;
     long long cheb_extra_ = 0;
     long long inner_total_ = 0;
     int switches_ = 0;
@@ -2102,9 +2135,13 @@ gsc_status solve_typed(Ctx &ctx, SolveRequest &req) {
 
     // tile width: all rhs if memory allows
     int Rt = o.rhs_tile > 0 ? o.rhs_tile : req.R;
+    // m = 16 unless asked otherwise: fewer passes over x^k, p^k for 2m
+    // seed-sized ring vectors per column
+    int m = o.fuse_steps > 0 ? std::min(o.fuse_steps, kMaxFuse) : (full ? kMaxFuse : 1);
+    if (!full) m = 1;
     if (full && o.rhs_tile <= 0) {
         const size_t freeb = dev_usable_bytes();
-        const double per_col = 2.0 * req.K * N * sizeof(cpx<T>) + 16.0 * N * sizeof(cpx<T>);
+        const double per_col = 2.0 * req.K * N * sizeof(cpx<T>) + (2.0 * m + 8.0) * N * sizeof(cpx<T>);
         const int fit = static_cast<int>(0.8 * static_cast<double>(freeb) / per_col);
         Rt = std::max(1, std::min(Rt, fit));
     }
@@ -2116,8 +2153,6 @@ gsc_status solve_typed(Ctx &ctx, SolveRequest &req) {
         Rt = std::max(64, std::min(Rt, fit));
     }
     Rt = std::max(1, std::min(Rt, req.R));
-    int m = o.fuse_steps > 0 ? std::min(o.fuse_steps, kMaxFuse) : (full ? 8 : 1);
-    if (!full) m = 1;
 
     std::vector<double> res_tmp;
     double *res_host = req.stats ? req.stats->res_recursive : nullptr;
