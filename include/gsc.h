@@ -114,7 +114,8 @@ typedef struct {
                               three vectors fit the 256 MB infinity cache
                               (no blocking when the tile already fits)        */
     int inner_relax;       /* [0] 1: relaxed inner tolerance (Chebyshev inner
-                              solves outside batched graphs): each outer
+                              solves; gsc_solve_batched captures a job's graph
+                              anew when its step count changes): each outer
                               iteration solves S r' = r to inner_tol divided
                               by the largest residual among the shifts still
                               above tol (at most 1e-6, at least inner_tol),

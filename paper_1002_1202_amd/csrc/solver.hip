@@ -1538,6 +1538,8 @@ template <typename T> class TileSolver {
         GSC_HIP(hipGetLastError());
         GSC_HIP(hipMemcpyAsync(h, d, sizeof(Status), hipMemcpyDeviceToHost, st_));
     }
+    // relaxed inner tolerance from a polled status (see relax_inner)
+    bool relax_from_status(const Status &s, bool steps_only) { return relax_inner(s.worst_res, steps_only); }
     void note_status(const Status &s) {
         flags_ |= s.flags;
         if (s.flags & FLAG_NAN) throw Error(GSC_E_NAN, "non-finite value in the iteration");
@@ -1806,6 +1808,9 @@ template <typename T> class TileSolver {
     }
 
     long long inner_total() const { return inner_total_; }
+    // graph replays run no host code: the scheduler keeps the count instead
+    void set_inner_total(long long v) { inner_total_ = v; }
+    int cheb_steps_per_solve() const { return cheb_steps_ - 1; }
     int switches() const { return switches_; }
     long long shift_rhs_iters() const { return shift_rhs_iters_; }
     double worst_res() const { return worst_res_; }
@@ -1923,12 +1928,17 @@ template <typename T> class TileSolver {
     // tol_in / (largest residual still above tol) therefore keeps what every
     // unconverged shift receives at tol_in relative to ||b||, as in its first
     // iteration.  Capped at kRelaxCap; the fixed tolerance is the floor.
-    void relax_inner(double worst) {
-        if (!cheb_ok_ || !(inner_tol_base_ > 0.0)) return;
+    // With steps_only, the tolerance changes only together with the step
+    // count (a captured graph holds both); returns whether the count changed.
+    bool relax_inner(double worst, bool steps_only = false) {
+        if (!cheb_ok_ || !(inner_tol_base_ > 0.0)) return false;
         double t = worst > 0.0 ? inner_tol_base_ / worst : inner_tol_base_;
         t = std::max(std::min(t, kRelaxCap), inner_tol_base_);
-        inner_tol_ = t;
-        cheb_steps_ = cheb_steps_for(t);
+        const int k = cheb_steps_for(t);
+        const bool changed = k != cheb_steps_;
+        if (changed || !steps_only) inner_tol_ = t;
+        cheb_steps_ = k;
+        return changed;
     }
 
     // Chebyshev iteration for S y = r (r in t_.r), y_K written to `ytarget`,
@@ -2261,6 +2271,14 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
         gsc_opts o{};
     };
     std::vector<Live> live(jobs.size());
+    auto capture = [graph_iters](Live &L, hipStream_t st) {
+        const long long counted = L.ts->inner_total();   // capturing runs nothing
+        GSC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        for (int g = 0; g < graph_iters; ++g) L.ts->enqueue_projected_iteration(L.o, 0);
+        GSC_HIP(hipStreamEndCapture(st, &L.graph));
+        GSC_HIP(hipGraphInstantiate(&L.exec, L.graph, nullptr, nullptr, 0));
+        L.ts->set_inner_total(counted);
+    };
     const bool prof_was_on = ctx.prof.on;
     ctx.prof.on = false;   // no event nodes inside captured graphs
     gsc_status result = GSC_OK;
@@ -2290,11 +2308,8 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
             L.dstat.alloc(1);
             GSC_HIP(hipHostMalloc(reinterpret_cast<void **>(&L.hstat), sizeof(Status), hipHostMallocDefault));
             if (L.ts->chebyshev_ready() && L.o.inner_method != 1) {
-                // capture graph_iters outer iterations once; replay until done
-                GSC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                for (int g = 0; g < graph_iters; ++g) L.ts->enqueue_projected_iteration(L.o, 0);
-                GSC_HIP(hipStreamEndCapture(st, &L.graph));
-                GSC_HIP(hipGraphInstantiate(&L.exec, L.graph, nullptr, nullptr, 0));
+                // capture graph_iters outer iterations; replay until done
+                capture(L, st);
                 L.graphed = true;
             }
         }
@@ -2310,6 +2325,8 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
                     if (L.graphed) {
                         GSC_HIP(hipGraphLaunch(L.exec, st));
                         L.n += graph_iters;
+                        L.ts->set_inner_total(L.ts->inner_total() +
+                                              static_cast<long long>(graph_iters) * L.ts->cheb_steps_per_solve());
                     } else {
                         L.ts->enqueue_projected_iteration(L.o, L.n);
                         L.n += 1;
@@ -2330,6 +2347,13 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
                 if (s.active_cols == 0 || L.n >= L.o.max_iter) {
                     L.finished = true;
                     --remaining;
+                } else if (L.o.inner_relax && L.ts->relax_from_status(s, L.graphed) && L.graphed) {
+                    // the graph holds the Chebyshev step count: capture anew
+                    (void)hipGraphExecDestroy(L.exec);
+                    (void)hipGraphDestroy(L.graph);
+                    L.exec = nullptr;
+                    L.graph = nullptr;
+                    capture(L, st);
                 }
             }
             if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));

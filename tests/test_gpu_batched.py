@@ -69,3 +69,25 @@ def test_batched_mixed_vs_oracle(ctx):
         print(f"  mixed iters={o['outer_iters']} G_jj err={err:.2e} dq={dq:.2e}", flush=True)
         assert err < 1e-3
         assert dq < 1e-3
+
+
+def test_batched_relaxed_inner_tolerance(ctx):
+    """inner_relax in the graph-captured batched solve: graphs are captured
+    anew as the Chebyshev step count falls; G_jj, q and e stay at the
+    fixed-tolerance bar against the oracle, with fewer inner steps (counted
+    per graph replay)."""
+    from paper_1002_1202_amd import api
+    print("case: batched fp64 inner_relax graph_iters=4", flush=True)
+    probs, refs = _problems(ctx)
+    fixed = api.solve_batched(ctx, probs, tol=1e-12, graph_iters=4)
+    relax = api.solve_batched(ctx, probs, tol=1e-12, graph_iters=4, inner_relax=True)
+    for o, f, (g0, q0, e0) in zip(relax, fixed, refs):
+        g = o["G_jj"].cpu().numpy()
+        err = np.abs(g - g0).max() / np.abs(g0).max()
+        print(f"  iters {f['outer_iters']} -> {o['outer_iters']} inner {f['inner_iters']} -> {o['inner_iters']} "
+              f"err={err:.2e}", flush=True)
+        assert o["converged"].all()
+        assert err < 1e-10
+        assert np.abs(o["q"].cpu().numpy() - q0).max() < 1e-10
+        assert np.abs(o["e"].cpu().numpy() - e0).max() < 1e-9
+        assert 0 < o["inner_iters"] < f["inner_iters"]

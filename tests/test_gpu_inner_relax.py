@@ -69,3 +69,30 @@ def test_relaxed_inner_tolerance_projected_charges(ctx):
                     inner_relax=True)
     ref = X[:, np.arange(4), rhs[:4]]
     assert rel(res.G_proj[sample, :, 0], ref) < 1e-9
+
+
+@pytest.mark.parametrize("case", ["si", "water"])
+def test_relaxed_inner_tolerance_band_energy_gradient(ctx, case):
+    """The backward (z-derivative carry) with the relaxed inner tolerance,
+    against the oracle's dense G S G gradient at the fixed-tolerance bar."""
+    from paper_1002_1202_amd import api
+    from synth.grids import shift_grid
+    if case == "si":
+        c = configs.si_small(cells=(2, 2, 2), seed=3)
+        z = shift_grid(-20.0, -6.65, 24, 0.2)
+    else:
+        c = configs.water_small(n_mol=24)
+        z = shift_grid(-40.0, -12.0, 24, 0.3)
+    s = c["system"]
+    w = trapezoid_weights(z)
+    print(f"case: vjp {case} N={s.n} K={len(z)} inner_relax", flush=True)
+    pair, _ = api.pair_from_system(ctx, s)
+    dH, dS, E, info = api.band_energy_vjp(ctx, pair, z, w, tol=1e-12, inner_relax=True)
+    _, _, E1, info1 = api.band_energy_vjp(ctx, pair, z, w, tol=1e-12)
+    S, H, _ = oased.dense_pair(s)
+    gH, gS = ogreen.band_energy_grad_dense(H, S, z, w)
+    rH, rS = rel(dH, oased.gather_blocks(s, gH)), rel(dS, oased.gather_blocks(s, gS))
+    print(f"  rel dH={rH:.2e} dS={rS:.2e} inner {info1['inner_iters']} -> {info['inner_iters']}", flush=True)
+    assert abs(E - E1) <= 1e-10 * abs(E1)
+    assert rH < 1e-9 and rS < 1e-9
+    assert info["inner_iters"] < info1["inner_iters"]
