@@ -105,7 +105,7 @@ def cpu_dense_lu(cfg, n_shifts=1):
                       f"{s.n}x{s.n} complex LU per shift)"}
 
 
-def forces_measure(name, n_slices=8, precision=None):
+def forces_measure(name, n_slices=8, precision=None, inner_relax=False):
     """One MD-style step at full size: the band energy over every orbital,
     its gradients on the stored H, S entries (one shifted solve with the
     z-derivative carry) and the forces through the ASED pair.  slab8192: FP64,
@@ -151,7 +151,7 @@ def forces_measure(name, n_slices=8, precision=None):
     t0 = time.perf_counter()
     for i, orbs in enumerate(slices):
         _, _, e, info = api.band_energy_vjp(ctx, pair, z, w, 1.0, dH, dS, orbs=orbs, tol=cfg["tol"],
-                                            precision=cfg["precision"])
+                                            precision=cfg["precision"], inner_relax=inner_relax)
         E += e
         iters = max(iters, info["outer_iters"])
         inner += info["inner_iters"]
@@ -167,6 +167,7 @@ def forces_measure(name, n_slices=8, precision=None):
     return {"metric": "band energy + forces, all orbitals", "workload": name,
             "system": f"{s.n_atoms} atoms, N={s.n}, nnzb={s.nnzb}, block={s.block}", "shifts": int(len(z)),
             "rhs": int(s.n), "slices": len(slices), "precision": cfg["precision"], "tol": cfg["tol"],
+            "inner_relax": bool(inner_relax),
             "e_fermi": ef, "seconds_solve_with_gradients": t1 - t0, "seconds_forces_from_gradients": t2 - t1,
             "outer_iters": iters, "inner_iters": inner, "shift_rhs_iters": work,
             "value": work / (t1 - t0), "unit": UNIT,
@@ -458,6 +459,8 @@ def main():
                          "orbital of a full-size workload (its own JSON line)")
     ap.add_argument("--forces-precision", default=None, choices=["fp64", "mixed"],
                     help="override the forces workload's precision (slab8192: fp64, water3000: mixed)")
+    ap.add_argument("--forces-inner-relax", action="store_true",
+                    help="run the forces workload with the relaxed inner tolerance (option inner_relax)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-dense-lu", action="store_true",
                     help="skip timing the dense-LU oracle on the host (one shift, all BLAS threads)")
@@ -488,7 +491,8 @@ def main():
         print(f"copy probe: {a.numel() * 8} bytes read and written", file=sys.stderr, flush=True)
         del a, b
     if args.forces:
-        print(json.dumps(forces_measure(args.forces, precision=args.forces_precision)), flush=True)
+        print(json.dumps(forces_measure(args.forces, precision=args.forces_precision,
+                                        inner_relax=args.forces_inner_relax)), flush=True)
         return
     if args.only == "batched":
         print(json.dumps(batched_compare(api.Context(0))), flush=True)
