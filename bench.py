@@ -227,6 +227,25 @@ def relax_compare(ctx, pair, s, z, rhs, Gc, tol, knobs):
             "converged_frac": float(np.mean(r.converged)), "rel_diff_vs_fixed_inner_tol": d / g}
 
 
+def host_output_step(ctx, pair, s, z, rhs, tol, knobs):
+    """One step with G returned in host memory (GSC_MEM_HOST): the copy of
+    every G column over PCIe is inside the timed region.  Reported beside
+    the headline, which keeps its outputs in HBM."""
+    import torch
+
+    from paper_1002_1202_amd import api
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    api.ased_build(ctx, pair, s)
+    r = api.solve(ctx, pair, z, rhs=rhs, out="host", tol=tol, **knobs)
+    dt = time.perf_counter() - t0
+    nbytes = r.G_cols.nbytes
+    del r
+    return {"ms_per_step": dt * 1e3, "value": None, "bytes_to_host": nbytes,
+            "note": "G columns (complex128, K x R x N) copied to pageable host memory"}
+
+
 def lanczos_compare(ctx, cfg):
     """G_jj of every right-hand side of the workload at every shift by the
     generalised Lanczos process + continued fraction (Sec. 3.2) and by the
@@ -465,6 +484,8 @@ def main():
     ap.add_argument("--no-dense-lu", action="store_true",
                     help="skip timing the dense-LU oracle on the host (one shift, all BLAS threads)")
     ap.add_argument("--no-lanczos", action="store_true")
+    ap.add_argument("--no-host-output", action="store_true",
+                    help="skip the step that returns G in host memory (PCIe-inclusive)")
     ap.add_argument("--no-relax", action="store_true",
                     help="skip the timed step with the relaxed inner tolerance")
     ap.add_argument("--no-scc", action="store_true")
@@ -607,6 +628,10 @@ def main():
     if not args.no_relax and args.precision == "fp64":
         line["inner_relax"] = relax_compare(ctx, pair, s, z, rhs, Gc, args.tol, knobs)
         print(f"inner_relax: {line['inner_relax']}", file=sys.stderr, flush=True)
+    if not args.no_host_output:
+        line["host_output"] = host_output_step(ctx, pair, s, z, rhs, args.tol, knobs)
+        line["host_output"]["value"] = results[-1].shift_rhs_iters / (line["host_output"]["ms_per_step"] * 1e-3)
+        print(f"host output: {line['host_output']['ms_per_step']:.0f} ms per step", file=sys.stderr, flush=True)
     del Gc
     torch.cuda.empty_cache()
     if not args.no_lanczos:
