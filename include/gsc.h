@@ -182,14 +182,16 @@ void gsc_opts_default(gsc_opts *opts);
  * hipStream_t (NULL = the null stream). */
 gsc_status gsc_create(gsc_ctx **out, int device, void *hip_stream);
 gsc_status gsc_set_stream(gsc_ctx *ctx, void *hip_stream);
-/* Destroys the context and hands the library's cached device blocks back to
- * the runtime. */
+/* Destroys the context and hands the library's cached device blocks and
+ * pinned staging buffers back to the runtime. */
 void gsc_destroy(gsc_ctx *ctx);
 /* The library keeps device blocks of 64 MiB and more after use (per device,
  * up to a third of its memory) and reuses them for later temporaries, so
  * that calls with changing sizes do not pay the driver's clearing of freshly
- * mapped memory.  This hands every cached block back to the runtime (for
- * callers that need the memory elsewhere); later calls allocate again. */
+ * mapped memory; bulk copies of G into host memory go through three pinned
+ * 256 MiB staging buffers kept likewise.  This hands every cached block and
+ * the staging buffers back to the runtime (for callers that need the memory
+ * elsewhere); later calls allocate again. */
 gsc_status gsc_release_cache(void);
 /* Thread-local description of the last failure ("" if none). */
 const char *gsc_last_error(void);

@@ -75,6 +75,11 @@ template <typename To, typename From> __host__ __device__ inline cpx<To> ccast(c
 // Cached blocks hold no data the caller can see.
 void *dev_alloc(size_t bytes);
 void dev_free(void *p);
+// Device-to-host copy into caller memory, stream-ordered after the work
+// already on `st`; returns when the data is in `dst`.  Copies of 256 MiB and
+// more go through pinned staging buffers drained by host threads.
+void copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t st);
+void host_staging_release();
 size_t dev_cache_bytes(int device);   // bytes cached for this device
 size_t dev_usable_bytes();            // free device memory plus this device's cache
 void dev_cache_release();             // hand every cached block back

@@ -139,9 +139,12 @@ size_t dev_usable_bytes() {
 }
 
 void dev_cache_release() {
-    Pool &P = pool();
-    std::lock_guard<std::mutex> lk(P.m);
-    release_locked(P, -1);
+    {
+        Pool &P = pool();
+        std::lock_guard<std::mutex> lk(P.m);
+        release_locked(P, -1);
+    }
+    host_staging_release();
 }
 
 }  // namespace gsc

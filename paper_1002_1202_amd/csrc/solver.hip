@@ -1719,12 +1719,15 @@ template <typename T> class TileSolver {
                     k_store_cols<T><<<div_up(tot, 256), 256, 0, st_>>>(td.K, td.R, td.N, t_.X, ldk_x_, tmp.get(),
                                                                       td.R, 0);
                     GSC_HIP(hipGetLastError());
-                    for (int k = 0; k < td.K; ++k)
-                        GSC_HIP(hipMemcpyAsync(req_.G_cols + 2 * ((static_cast<size_t>(k) * nrhs_total + r0_) * td.N),
-                                               tmp.get() + static_cast<size_t>(k) * td.R * td.N,
-                                               static_cast<size_t>(td.R) * td.N * sizeof(c128),
-                                               hipMemcpyDeviceToHost, st_));
-                    GSC_HIP(hipStreamSynchronize(st_));
+                    const size_t slab = static_cast<size_t>(td.R) * td.N * sizeof(c128);
+                    if (td.R == nrhs_total) {
+                        // one tile: the whole [K][R][N] block is contiguous on both sides
+                        copy_to_host(req_.G_cols, tmp.get(), slab * td.K, st_);
+                    } else {
+                        for (int k = 0; k < td.K; ++k)
+                            copy_to_host(req_.G_cols + 2 * ((static_cast<size_t>(k) * nrhs_total + r0_) * td.N),
+                                         tmp.get() + static_cast<size_t>(k) * td.R * td.N, slab, st_);
+                    }
                 }
             }
             if (req_.G_proj != nullptr && req_.nproj > 0) {
