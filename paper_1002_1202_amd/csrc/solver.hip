@@ -1335,12 +1335,14 @@ template <typename T> struct Tile {
     }
 };
 
+// Status record in pinned host memory; k_status writes it through its
+// device mapping (no copy after the reduction).
 struct HostStatus {
     Status *h = nullptr;
-    DevBuf<Status> d;
+    Status *hd = nullptr;   // device address of h
     HostStatus() {
         GSC_HIP(hipHostMalloc(reinterpret_cast<void **>(&h), sizeof(Status), hipHostMallocDefault));
-        d.alloc(1);
+        GSC_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&hd), h, 0));
     }
     ~HostStatus() {
         if (h) (void)hipHostFree(h);
@@ -1866,9 +1868,8 @@ template <typename T> class TileSolver {
 
     Status check_status(bool count_switch) {
         auto &td = t_.td;
-        k_status<<<1, kBlock, 0, st_>>>(td.Rp, t_.cols(), hs_.d.get());
+        k_status<<<1, kBlock, 0, st_>>>(td.Rp, t_.cols(), hs_.hd);
         GSC_HIP(hipGetLastError());
-        GSC_HIP(hipMemcpyAsync(hs_.h, hs_.d.get(), sizeof(Status), hipMemcpyDeviceToHost, st_));
         GSC_HIP(hipStreamSynchronize(st_));
         const Status s = *hs_.h;
         flags_ |= s.flags;
