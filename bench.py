@@ -58,6 +58,24 @@ def describe(cfg, args):
     }
 
 
+def host_cpu():
+    """CPU model and the cores this process may use (for the oracle timings)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
 def cpu_baseline(cfg, iters):
     """Oracle model of the method (oracle/shifted_cocg.py) on one rhs and all
     shifts of the workload, for a fixed number of outer iterations."""
@@ -75,7 +93,7 @@ def cpu_baseline(cfg, iters):
         t0 = time.perf_counter()
         r = shifted_cocg.solve(H, S, cfg["z"], b, tol=1e-10, max_iter=iters)
         dt = time.perf_counter() - t0
-    return {"value": r.active_shift_iters / dt, "unit": UNIT, "cores": 1, "kind": "oracle",
+    return {"value": r.active_shift_iters / dt, "unit": UNIT, "cores": 1, "kind": "oracle", "host": host_cpu(),
             "sample": f"oracle step-by-step model (numpy/scipy, 1 thread), workload {cfg['name']}, "
                       f"1 rhs x {len(cfg['z'])} shifts x {r.iters} outer iterations "
                       f"({r.active_shift_iters} active shift-iterations, {r.inner_iters} inner CG "
@@ -99,7 +117,7 @@ def cpu_dense_lu(cfg, n_shifts=1):
     green.solve_dense(H, S, z, cfg["rhs"])
     dt = (time.perf_counter() - t0) / n_shifts
     threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
-    return {"kind": "oracle dense LU (numpy/scipy LAPACK)", "threads": threads,
+    return {"kind": "oracle dense LU (numpy/scipy LAPACK)", "threads": threads, "host": host_cpu(),
             "seconds_per_shift": dt, "extrapolated_seconds_all_shifts": dt * len(cfg["z"]),
             "sample": f"{n_shifts} shift(s) x {len(cfg['rhs'])} rhs of {cfg['name']} (N={s.n}, dense "
                       f"{s.n}x{s.n} complex LU per shift)"}
