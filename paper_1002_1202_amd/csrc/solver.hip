@@ -134,12 +134,15 @@ __global__ __launch_bounds__(kBlock) void k_init_rhs(int N, int Rp, int Lr, int 
 }
 
 template <typename T>
-__global__ void k_zero_shifted(int K, int R, int N, size_t ldk, cpx<T> *X) {
-    const int64_t per = static_cast<int64_t>(R) * N;
-    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= per * K) return;
-    const int64_t k = t / per, o = t % per;
-    X[k * ldk + o] = {0, 0};
+__global__ void k_zero_done_cols(int K, int R, int N, size_t ldk, const int *done, cpx<T> *X) {
+    // x^k = 0 for every shift of a column that is done before its first
+    // step (b = 0); every other column's x^k is written by its first pass
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int c = blockIdx.y; c < R; c += gridDim.y) {
+        if (!done[c]) continue;
+        for (int k = 0; k < K; ++k) X[static_cast<size_t>(k) * ldk + static_cast<size_t>(c) * N + i] = {0, 0};
+    }
 }
 
 // ------------------------------------------------------------------ column kernels
@@ -793,9 +796,13 @@ __global__ __launch_bounds__(kBlock) void k_flush(int N, int Rp, int K, int m, i
     const int col = blockIdx.y;
     if (col >= R) return;
     if (only_sw && cs.sw[col] != 1) return;
+    if (cs.iters[col] == 0) return;   // b = 0: the column never took a step, x^k = 0
     const int tb = max(n0, cs.applied[col]);
     const int cnt = n1 - tb;
     if (cnt <= 0) return;
+    // a pass from step 0 is the column's first: x^k = p^k = 0 before it, so
+    // they are not read (nor zeroed beforehand)
+    const bool fresh = tb == 0;
     ActiveShifts act{K, Rp, col, tb, n1};
     act.last = ss.last;
     int k, kc;
@@ -807,8 +814,8 @@ __global__ __launch_bounds__(kBlock) void k_flush(int N, int Rp, int K, int m, i
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int i = ibase + e * kBlock;
-            pv[e] = i < N ? P[static_cast<size_t>(kk) * ldp + base + i] : cpx<T>{0, 0};
-            xv[e] = i < N ? X[static_cast<size_t>(kk) * ldx + base + i] : cpx<T>{0, 0};
+            pv[e] = (i < N && !fresh) ? P[static_cast<size_t>(kk) * ldp + base + i] : cpx<T>{0, 0};
+            xv[e] = (i < N && !fresh) ? X[static_cast<size_t>(kk) * ldx + base + i] : cpx<T>{0, 0};
         }
     };
     cpx<T> pv[E], xv[E];
@@ -1472,11 +1479,6 @@ template <typename T> class TileSolver {
         }
         k_init_cols<<<cb, 256, 0, st_>>>(td.R, td.Rp, seed0, cs);
         k_init_shifts<<<div_up(static_cast<int64_t>(td.K) * td.Rp, 256), 256, 0, st_>>>(td.K, td.R, td.Rp, ss);
-        if (full_) {
-            const int64_t tot = static_cast<int64_t>(td.R) * td.N * td.K;
-            k_zero_shifted<T><<<div_up(tot, 256), 256, 0, st_>>>(td.K, td.R, td.N, t_.ldk, t_.P.get());
-            k_zero_shifted<T><<<div_up(tot, 256), 256, 0, st_>>>(td.K, td.R, td.N, ldk_x_, t_.X);
-        }
         if (t_.h.get()) GSC_HIP(hipMemsetAsync(t_.h.get(), 0, t_.h.n * sizeof(c128), st_));
         if (t_.gacc.get()) GSC_HIP(hipMemsetAsync(t_.gacc.get(), 0, t_.gacc.n * sizeof(c128), st_));
         if (t_.dh.get()) GSC_HIP(hipMemsetAsync(t_.dh.get(), 0, t_.dh.n * sizeof(c128), st_));
@@ -1485,6 +1487,9 @@ template <typename T> class TileSolver {
         k_init_rhs<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, td.R, drhs_, dB_, t_.r.get(), t_.res.get(),
                                          t_.d.get(), t_.part_d.get());
         k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 1, inner_tol, cs);
+        if (full_)
+            k_zero_done_cols<T><<<dim3(div_up(td.N, 256), std::min(td.R, 1024)), 256, 0, st_>>>(
+                td.K, td.R, td.N, ldk_x_, t_.c_done.get(), t_.X);
         inner_tol_ = inner_tol;
         inner_tol_base_ = inner_tol;
         inner_solve_cg(o, cs, t_.ring.get());

@@ -163,3 +163,29 @@ def test_maximum_projection_count(ctx):
     X = ogreen.solve_dense(H, S, c["z"], rhs)
     ref = np.take_along_axis(X, np.broadcast_to(proj[None], (X.shape[0],) + proj.shape), axis=2)
     assert rel(res.G_proj, ref) < 1e-10
+
+
+def test_dense_rhs_with_a_zero_column(ctx):
+    """Dense right-hand sides, one of them zero: that column is finished
+    before its first step and its x^k must be exactly 0 for every shift (its
+    shift coefficients are never formed); the others against the dense
+    inverse.  Run twice so the second solve reuses the first one's blocks."""
+    from paper_1002_1202_amd import api
+    print("case: si64 dense B with a zero column", flush=True)
+    c = configs.si_small(cells=(2, 2, 2), n_shift=12, eta=0.2, seed=9)
+    s = c["system"]
+    S, H, _ = oased.dense_pair(s)
+    pair, _ = api.pair_from_system(ctx, s)
+    rng = np.random.default_rng(12)
+    B = rng.standard_normal((5, s.n)) + 1j * rng.standard_normal((5, s.n))
+    B[2] = 0.0
+    z = c["z"]
+    ref = np.stack([np.linalg.solve(zk * S - H, B.T).T for zk in z])     # [K][R][N]
+    for _ in range(2):
+        res = api.solve(ctx, pair, z, B=B, tol=1e-12)
+        assert res.status == 0
+        assert np.all(res.G_cols[:, 2] == 0)
+        assert rel(res.G_cols, ref) < 1e-10
+        resp = api.solve(ctx, pair, z, B=B, tol=1e-12, carry="projected", proj=np.tile(np.arange(4), (5, 1)))
+        assert np.all(resp.G_proj[:, 2] == 0)
+        assert rel(resp.G_proj, ref[:, :, :4]) < 1e-10
