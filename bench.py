@@ -513,7 +513,7 @@ def main():
                          "which calibrates the HBM byte counters of a --pmc run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no collectives, no sharding); "
+        print("bench.py: the library runs on one GPU only (no collectives, no sharding); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -187,8 +187,8 @@ gsc_status gsc_set_stream(gsc_ctx *ctx, void *hip_stream);
 void gsc_destroy(gsc_ctx *ctx);
 /* The library keeps device blocks of 64 MiB and more after use (per device,
  * up to a third of its memory) and reuses them for later temporaries, so
- * that calls with changing sizes do not pay the driver's clearing of freshly
- * mapped memory; bulk copies of G into host memory go through three pinned
+ * that calls with changing sizes do not pay the kernel driver's clearing of
+ * freshly mapped memory; bulk copies of G into host memory go through three pinned
  * 256 MiB staging buffers kept likewise.  This hands every cached block and
  * the staging buffers back to the runtime (for callers that need the memory
  * elsewhere); later calls allocate again. */

@@ -68,9 +68,9 @@ template <typename To, typename From> __host__ __device__ inline cpx<To> ccast(c
 // Every library temporary comes from dev_alloc.  Blocks of at least 64 MiB
 // are kept after dev_free (per device, up to a third of its memory) and
 // handed to later requests of at most their size and at least half of it:
-// freshly mapped device memory is cleared by the driver, which for the tens
-// of GB of a full-carry solve costs about a second whenever the sizes of
-// consecutive calls differ.  Like hipFree, dev_free of such a block waits
+// freshly mapped device memory is cleared by the amdgpu kernel driver,
+// which for the tens of GB of a full-carry solve costs about a second
+// whenever the sizes of consecutive calls differ.  Like hipFree, dev_free of such a block waits
 // for the device to go idle before the block can be handed out again.
 // Cached blocks hold no data the caller can see.
 void *dev_alloc(size_t bytes);
