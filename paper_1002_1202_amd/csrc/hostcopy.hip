@@ -43,7 +43,11 @@ void parallel_copy(char *dst, const char *src, size_t len) {
     for (int t = 0; t < nt; ++t) {
         const size_t o = std::min(len, static_cast<size_t>(t) * part);
         const size_t l = std::min(len - o, part);
-        th.emplace_back([=] { std::memcpy(dst + o, src + o, l); });
+        try {
+            th.emplace_back([=] { std::memcpy(dst + o, src + o, l); });
+        } catch (...) {
+            std::memcpy(dst + o, src + o, l);   // no thread available: copy this part here
+        }
     }
     for (auto &x : th) x.join();
 }

@@ -1053,7 +1053,8 @@ __global__ void k_true_residual(int K, int R, int N, int B, const int32_t *rowpt
     }
     const double ta = block_sum(acc, lds);
     const double tb = block_sum(bb, lds);
-    if (threadIdx.x == 0) out[static_cast<size_t>(k) * R + c] = sqrt(ta) / sqrt(tb);
+    // b = 0: x = 0 is exact (relative residual 0)
+    if (threadIdx.x == 0) out[static_cast<size_t>(k) * R + c] = tb > 0.0 ? sqrt(ta) / sqrt(tb) : sqrt(ta);
 }
 
 // ------------------------------------------------------------------ driver

@@ -182,10 +182,12 @@ def test_dense_rhs_with_a_zero_column(ctx):
     z = c["z"]
     ref = np.stack([np.linalg.solve(zk * S - H, B.T).T for zk in z])     # [K][R][N]
     for _ in range(2):
-        res = api.solve(ctx, pair, z, B=B, tol=1e-12)
+        res = api.solve(ctx, pair, z, B=B, tol=1e-12, recheck=True)
         assert res.status == 0
         assert np.all(res.G_cols[:, 2] == 0)
         assert rel(res.G_cols, ref) < 1e-10
+        assert np.all(res.res_true[:, 2] == 0) and np.all(np.isfinite(res.res_true))
+        assert res.res_true.max() < 1e-10
         resp = api.solve(ctx, pair, z, B=B, tol=1e-12, carry="projected", proj=np.tile(np.arange(4), (5, 1)))
         assert np.all(resp.G_proj[:, 2] == 0)
         assert rel(resp.G_proj, ref[:, :, :4]) < 1e-10
