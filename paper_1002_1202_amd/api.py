@@ -199,6 +199,12 @@ def make_opts(tol=1e-10, max_iter=5000, inner_tol=0.0, inner_max_iter=200, preci
               carry="full", seed_index=-1, fuse_steps=0, rhs_tile=0, recheck=False,
               spmm_kernel=0, inner_method=0, graph_iters=0, stream_hint=0, cheb_block=0,
               inner_relax=False) -> L.Opts:
+    """gsc_opts with the library's defaults for every option not given (the
+    fields and their meaning are those of gsc_opts in include/gsc.h).
+    ``precision``: "fp64" or "mixed" (complex64 products, FP64 recurrences);
+    ``carry``: "full" (every x^k) or "projected"; ``inner_relax``: relaxed
+    inner tolerance (off by default: the fixed inner tolerance of the
+    method)."""
     o = L.Opts()
     L.load().gsc_opts_default(C.byref(o))
     o.tol, o.max_iter, o.inner_tol, o.inner_max_iter = tol, max_iter, inner_tol, inner_max_iter
