@@ -73,3 +73,24 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(out[cname]) == C.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_option_defaults_and_binding():
+    """gsc_opts_default (a host function) gives the defaults the header
+    documents, and make_opts writes every option into its own field."""
+    from paper_1002_1202_amd import _lib, api
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libgsc.so not built")
+    o = _lib.Opts()
+    _lib.load().gsc_opts_default(C.byref(o))
+    assert (o.tol, o.max_iter, o.inner_tol, o.inner_max_iter) == (1e-10, 5000, 0.0, 200)
+    assert (o.precision, o.carry, o.seed_index) == (_lib.FP64, _lib.CARRY_FULL, -1)
+    for f in ("fuse_steps", "rhs_tile", "recheck", "spmm_kernel", "inner_method", "graph_iters",
+              "stream_hint", "cheb_block", "inner_relax"):
+        assert getattr(o, f) == 0, f
+    assert list(o.reserved) == [0, 0]
+    m = api.make_opts(tol=1e-6, fuse_steps=12, cheb_block=128, inner_relax=True, graph_iters=8,
+                      precision="mixed", carry="projected")
+    assert (m.tol, m.fuse_steps, m.cheb_block, m.inner_relax, m.graph_iters) == (1e-6, 12, 128, 1, 8)
+    assert (m.precision, m.carry) == (_lib.MIXED, _lib.CARRY_PROJECTED)
+    assert list(m.reserved) == [0, 0]
