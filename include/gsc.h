@@ -234,8 +234,10 @@ gsc_status gsc_spmm(gsc_ctx *ctx, const gsc_pair *pair, int nrhs, const double *
                     const double *X, double *Y, int mem);
 
 /* ---- the shifted solve (Sec. 3.3) ---------------------------------------- */
-/* rhs: unit vectors e_{rhs_idx[r]} (rhs_idx HOST [nrhs]) or, if rhs_idx is
- * NULL, dense columns B_dense[r][N] complex (per out_mem).
+/* 1 <= nshift <= 65535 (every entry point that takes shifts).
+ * rhs: unit vectors e_{rhs_idx[r]} (rhs_idx HOST [nrhs]) or, if rhs_idx is
+ * NULL, dense columns B_dense[r][N] complex (per out_mem); any nrhs (the
+ * full carry runs at most 65472 columns per device tile).
  * Outputs (per out_mem; either may be NULL):
  *   G_cols [nshift][nrhs][N] complex   = x_k for rhs r   (full carry only)
  *   G_proj [nshift][nrhs][nproj] complex = (x_k)_{proj_idx[r][m]}

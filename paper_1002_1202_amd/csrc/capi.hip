@@ -126,6 +126,7 @@ void validate_opts(const gsc_opts &o) {
 
 void validate_shifts(int nshift, const double *z, int seed_index) {
     GSC_REQUIRE(nshift >= 1 && z != nullptr, "need at least one shift");
+    GSC_REQUIRE(nshift <= 65535, "at most 65535 shifts per call");
     for (int k = 0; k < nshift; ++k) {
         GSC_REQUIRE(std::isfinite(z[2 * k]) && std::isfinite(z[2 * k + 1]), "shifts must be finite");
         GSC_REQUIRE(z[2 * k + 1] > 0.0, "every shift needs Im z > 0 (z S - H must be nonsingular)");

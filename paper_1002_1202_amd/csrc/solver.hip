@@ -2173,6 +2173,9 @@ gsc_status solve_typed(Ctx &ctx, SolveRequest &req) {
         Rt = std::max(64, std::min(Rt, fit));
     }
     Rt = std::max(1, std::min(Rt, req.R));
+    // the shift-update pass launches one grid row per column of the tile
+    // (at most 65535); wider requests run in several tiles
+    if (full) Rt = std::min(Rt, 65472);
 
     std::vector<double> res_tmp;
     double *res_host = req.stats ? req.stats->res_recursive : nullptr;

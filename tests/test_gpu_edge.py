@@ -140,6 +140,7 @@ def test_empty_inputs_and_limits_are_rejected(ctx):
         "1025 projections": lambda: api.solve(ctx, pair, z, rhs=[0], carry="projected",
                                               proj=np.zeros((1, 1025), np.int64)),
         "lanczos m_max 0": lambda: api.lanczos_green(ctx, pair, z, [0], m_max=0),
+        "65536 shifts": lambda: api.solve(ctx, pair, np.full(65536, -5.0 + 0.1j), rhs=[0]),
     }
     for name, call in cases.items():
         with pytest.raises((_lib.GscError, ValueError)) as e:
@@ -191,3 +192,23 @@ def test_dense_rhs_with_a_zero_column(ctx):
         resp = api.solve(ctx, pair, z, B=B, tol=1e-12, carry="projected", proj=np.tile(np.arange(4), (5, 1)))
         assert np.all(resp.G_proj[:, 2] == 0)
         assert rel(resp.G_proj, ref[:, :, :4]) < 1e-10
+
+
+def test_full_carry_wider_than_one_tile(ctx):
+    """65,600 right-hand sides in full carry: more columns than one device
+    tile takes (65,472), so the solve runs in two tiles; every column against
+    the dense inverse."""
+    from paper_1002_1202_amd import api
+    print("case: si8 K=2, 65600 rhs (two full-carry tiles)", flush=True)
+    c = configs.si_small(cells=(1, 1, 1), n_shift=2, eta=0.2, seed=13)
+    s = c["system"]
+    S, H, _ = oased.dense_pair(s)
+    pair, _ = api.pair_from_system(ctx, s)
+    rhs = np.arange(65600, dtype=np.int64) % s.n
+    z = c["z"]
+    res = api.solve(ctx, pair, z, rhs=rhs, tol=1e-12)
+    assert res.status == 0 and res.converged.all()
+    inv = np.stack([np.linalg.inv(zk * S - H) for zk in z])          # [K][N][N]
+    ref = inv[:, :, rhs].transpose(0, 2, 1)                          # [K][R][N]
+    print(f"  err={rel(res.G_cols, ref):.2e}", flush=True)
+    assert rel(res.G_cols, ref) < 1e-10
