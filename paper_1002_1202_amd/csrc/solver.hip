@@ -711,18 +711,23 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_ring_transpose(int N, int Rp, const cpx<T> *__restrict__ src,
                                                            cpx<T> *__restrict__ dst) {
     __shared__ cpx<T> tile[64][33];
-    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 32;
+    const int c0 = blockIdx.x * 64;
     const int t = threadIdx.x;
+    // 32-row tiles, strided over the grid's second dimension (uniform trip
+    // count per block, so the barriers are reached by every thread)
+    for (int r0 = blockIdx.y * 32; r0 < N; r0 += gridDim.y * 32) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int c = t & 63, r = (t >> 6) + 4 * j;
-        if (r0 + r < N) tile[c][r] = src[static_cast<size_t>(r0 + r) * Rp + c0 + c];
-    }
-    __syncthreads();
+        for (int j = 0; j < 8; ++j) {
+            const int c = t & 63, r = (t >> 6) + 4 * j;
+            if (r0 + r < N) tile[c][r] = src[static_cast<size_t>(r0 + r) * Rp + c0 + c];
+        }
+        __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int r = t & 31, c = (t >> 5) + 8 * j;
-        if (r0 + r < N) dst[static_cast<size_t>(c0 + c) * N + r0 + r] = tile[c][r];
+        for (int j = 0; j < 8; ++j) {
+            const int r = t & 31, c = (t >> 5) + 8 * j;
+            if (r0 + r < N) dst[static_cast<size_t>(c0 + c) * N + r0 + r] = tile[c][r];
+        }
+        __syncthreads();
     }
 }
 
@@ -1495,7 +1500,7 @@ template <typename T> class TileSolver {
         inner_tol_base_ = inner_tol;
         inner_solve_cg(o, cs, t_.ring.get());
         if (full_) {
-            k_ring_transpose<T><<<dim3(td.Rp / 64, div_up(td.N, 32)), kBlock, 0, st_>>>(td.N, td.Rp, t_.ring.get(),
+            k_ring_transpose<T><<<dim3(td.Rp / 64, std::min(div_up(td.N, 32), 65535)), kBlock, 0, st_>>>(td.N, td.Rp, t_.ring.get(),
                                                                                       t_.ringT.get());
         }
         if (o.inner_method != 1) setup_chebyshev(o, inner_tol);
@@ -1622,7 +1627,7 @@ template <typename T> class TileSolver {
             prof_.end(st_);
             if (full_ && !fuse_t) {
                 prof_.begin(st_, KP_RING_T, 0.0);
-                k_ring_transpose<T><<<dim3(td.Rp / 64, div_up(td.N, 32)), kBlock, 0, st_>>>(
+                k_ring_transpose<T><<<dim3(td.Rp / 64, std::min(div_up(td.N, 32), 65535)), kBlock, 0, st_>>>(
                     td.N, td.Rp, rp_next, t_.ringT.get() + slot_next * NR);
                 prof_.end(st_);
             }

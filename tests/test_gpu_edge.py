@@ -212,3 +212,36 @@ def test_full_carry_wider_than_one_tile(ctx):
     ref = inv[:, :, rhs].transpose(0, 2, 1)                          # [K][R][N]
     print(f"  err={rel(res.G_cols, ref):.2e}", flush=True)
     assert rel(res.G_cols, ref) < 1e-10
+
+
+def test_ring_copy_by_transpose_kernel():
+    """1,024 right-hand sides of a 3,072-atom cell in one tile: more than 64
+    rows per row group, so the column-major copy of r' is made by its own
+    transpose kernel instead of inside the p update.  Against the same solve
+    in 256-column tiles (the fused copy) and sampled true residuals with the
+    oracle's sparse S and H."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1002_1202_amd import api
+    print("case: si3072 K=4 R=1024, ring copy by the transpose kernel", flush=True)
+    ctx = api.Context(0)
+    c = configs.si_small(cells=(8, 8, 6), n_shift=4, eta=0.2, n_rhs=1024, seed=25)
+    s = c["system"]
+    z, rhs = c["z"], c["rhs"]
+    pair, _ = api.pair_from_system(ctx, s)
+    wide = api.solve(ctx, pair, z, rhs=rhs, tol=1e-10)
+    tiled = api.solve(ctx, pair, z, rhs=rhs, tol=1e-10, rhs_tile=256)
+    assert wide.converged.all() and tiled.converged.all()
+    d = rel(wide.G_cols, tiled.G_cols)
+    Sb, Hb, _ = oased.pair_blocks(s)
+    S, H = ogreen.sparse_matrices(s, Sb, Hb)
+    worst = 0.0
+    for k, r in [(0, 0), (1, 517), (3, 1023)]:
+        x = wide.G_cols[k, r]
+        b = np.zeros(s.n, complex)
+        b[rhs[r]] = 1.0
+        worst = max(worst, float(np.linalg.norm(b - (z[k] * (S @ x) - H @ x))))
+    print(f"  wide vs 256-column tiles {d:.2e}, sampled true residual {worst:.2e}", flush=True)
+    assert d < 1e-8          # both converged to tol 1e-10; a wrong copy gives O(1)
+    assert worst < 1e-8
