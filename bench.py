@@ -484,7 +484,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=300)
     ap.add_argument("--spmm", type=int, default=0,
-                    help="0 auto, 1 row kernel, 2 cluster, 3 slab, 4 split-orbital Chebyshev")
+                    help="0 auto, 1 row kernel (the only layout)")
     ap.add_argument("--inner", type=int, default=0, help="0 auto, 1 CG, 2 Chebyshev")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate launch shapes on this problem first and use the fastest")

@@ -86,15 +86,7 @@ typedef struct {
     int recheck;           /* [0] 1: FP64 true residual of every (k, rhs) into
                               gsc_stats.res_true (full carry only)             */
     int spmm_kernel;       /* [0 = auto = 1] product kernel layout: 1 one block
-                              row x 64 rhs per wave, 2 register-blocked
-                              clusters of block rows sharing x loads, 3 one
-                              block row x a 16-rhs slab per wave with each
-                              XCD sweeping its slabs in row order, 4 as 1
-                              except the Chebyshev step, which takes one
-                              block row x 32 rhs per wave (each half-wave
-                              half of the block's orbitals), one XCD per
-                              32-rhs stripe when there are 8 stripes (256
-                              padded rhs)                                     */
+                              row x 64 rhs per wave (the only layout)         */
     int inner_method;      /* [0 = auto] inner solver for S r' = r: 1 CG (the
                               first solve always runs CG), 2 Chebyshev on the
                               interval of the first CG solve's Ritz values

@@ -20,7 +20,6 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg
 import scipy.sparse
-import scipy.sparse.linalg
 
 
 def _rhs_matrix(n: int, rhs_idx=None, B_dense=None) -> np.ndarray:
@@ -55,19 +54,6 @@ def sparse_matrices(system, Sb: np.ndarray, Hb: np.ndarray):
     S = scipy.sparse.csr_matrix((Sb.reshape(-1), (r.reshape(-1), c.reshape(-1))), shape=shape)
     H = scipy.sparse.csr_matrix((Hb.reshape(-1), (r.reshape(-1), c.reshape(-1))), shape=shape)
     return S, H
-
-
-def solve_sparse(H, S, z, rhs_idx=None, B_dense=None) -> np.ndarray:
-    """Same as ``solve_dense`` with a sparse LU (SuperLU) per shift."""
-    n = H.shape[0]
-    Bm = _rhs_matrix(n, rhs_idx, B_dense)
-    z = np.atleast_1d(np.asarray(z, dtype=np.complex128))
-    X = np.empty((z.shape[0], Bm.shape[1], n), dtype=np.complex128)
-    for k, zk in enumerate(z):
-        A = (zk * S - H).astype(np.complex128).tocsc()
-        lu = scipy.sparse.linalg.splu(A)
-        X[k] = lu.solve(Bm).T
-    return X
 
 
 def mulliken_band(S, X: np.ndarray, z, w, rhs_idx):
@@ -126,16 +112,3 @@ def charge_grad_dense(H, S, z, w, orbs, qbar):
         gH += -(2.0 / np.pi) * wk * GSQG.imag
         gS += -(2.0 / np.pi) * wk * (Q @ G - zk * GSQG).imag
     return gH, gS
-
-
-def true_residual(H, S, z, X, rhs_idx=None, B_dense=None):
-    """||b - (z_k S - H) x_k||_2 / ||b||_2 for every (k, r)."""
-    n = H.shape[0]
-    Bm = _rhs_matrix(n, rhs_idx, B_dense)
-    K, R, _ = X.shape
-    out = np.empty((K, R))
-    for k in range(K):
-        A = z[k] * S - H
-        res = Bm - A @ X[k].T
-        out[k] = np.linalg.norm(res, axis=0) / np.linalg.norm(Bm, axis=0)
-    return out

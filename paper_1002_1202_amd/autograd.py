@@ -5,8 +5,10 @@ ASED pair.
 forward (E_band together with dE/dH and dE/dS, the backward reusing the same
 shifted solver); its backward only scales the stored gradients by the
 incoming scalar.  ``MullikenCharges`` returns the charges of listed orbitals;
-its backward solves for G e_a and G S e_a and contracts them with the
-incoming charge gradient on the pattern (the general charge-loss adjoint).
+its backward puts the forward's H, S back into the pair (which other calls
+may have changed meanwhile), solves for G e_a and G S e_a and contracts them
+with the incoming charge gradient on the pattern (the general charge-loss
+adjoint).
 ``AsedPair`` builds S, H on the device from positions and maps (dE/dH,
 dE/dS) to dE/dpos with the library's VJP kernels.
 """
@@ -38,14 +40,21 @@ class BandEnergy(torch.autograd.Function):
 class MullikenCharges(torch.autograd.Function):
     @staticmethod
     def forward(fctx, Hval, Sval, gctx, pair, z, w, orbs, opts):
-        pair.set_values(Hval.detach().contiguous(), Sval.detach().contiguous())
+        H = Hval.detach().contiguous()
+        S = Sval.detach().contiguous()
+        pair.set_values(H, S)
         q, _, _, info = api.mulliken_band(gctx, pair, z, w, orbs, **opts)
+        # the pair is shared: another forward may change its values before
+        # this backward runs, so the values of this forward are kept
+        fctx.save_for_backward(H, S)
         fctx.gctx, fctx.pair, fctx.z, fctx.w, fctx.orbs, fctx.opts = gctx, pair, z, w, orbs, opts
         fctx.info = info
         return torch.from_numpy(q).to(Hval.device)
 
     @staticmethod
     def backward(fctx, gq):
+        H, S = fctx.saved_tensors
+        fctx.pair.set_values(H, S)
         qbar = gq.detach().cpu().numpy().astype(np.float64)
         shape = (fctx.pair.nnzb, fctx.pair.block, fctx.pair.block)
         dH = torch.zeros(shape, dtype=torch.float64, device=gq.device)

@@ -22,16 +22,14 @@ KNOBS_FULL = [
     dict(fuse_steps=16, spmm_kernel=1, inner_method=2),
     dict(fuse_steps=12, spmm_kernel=1, inner_method=2),
     dict(fuse_steps=8, spmm_kernel=1, inner_method=2),
-    dict(fuse_steps=16, spmm_kernel=4, inner_method=2),
     dict(fuse_steps=16, spmm_kernel=1, inner_method=1),
 ]
 KNOBS_PROJECTED = [
     dict(spmm_kernel=1, inner_method=2),
-    dict(spmm_kernel=4, inner_method=2),
     dict(spmm_kernel=1, inner_method=1),
 ]
 KNOBS_BATCHED = [
-    dict(graph_iters=4), dict(graph_iters=1), dict(graph_iters=8), dict(graph_iters=4, spmm_kernel=1),
+    dict(graph_iters=4), dict(graph_iters=1), dict(graph_iters=8),
 ]
 
 

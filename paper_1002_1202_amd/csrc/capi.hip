@@ -117,7 +117,7 @@ void validate_opts(const gsc_opts &o) {
     GSC_REQUIRE(o.precision == GSC_FP64 || o.precision == GSC_MIXED, "unknown precision");
     GSC_REQUIRE(o.carry == GSC_CARRY_FULL || o.carry == GSC_CARRY_PROJECTED, "unknown carry mode");
     GSC_REQUIRE(o.fuse_steps >= 0 && o.fuse_steps <= kMaxFuse, "fuse_steps must be in [0, 16]");
-    GSC_REQUIRE(o.spmm_kernel >= 0 && o.spmm_kernel <= 4, "spmm_kernel must be 0 .. 4");
+    GSC_REQUIRE(o.spmm_kernel >= 0 && o.spmm_kernel <= 1, "spmm_kernel must be 0 or 1");
     GSC_REQUIRE(o.stream_hint >= 0 && o.stream_hint <= 2, "stream_hint must be 0, 1 or 2");
     GSC_REQUIRE(o.cheb_block >= 0 && o.cheb_block % 64 == 0, "cheb_block must be 0 or a multiple of 64");
     GSC_REQUIRE(o.inner_relax == 0 || o.inner_relax == 1, "inner_relax must be 0 or 1");
@@ -304,7 +304,7 @@ gsc_status gsc_spmm(gsc_ctx *ctx, const gsc_pair *pair, int nrhs, const double *
         GSC_HIP(hipMemcpyAsync(dseed.get(), iota.data(), Rp * sizeof(int), hipMemcpyHostToDevice, st));
         TileDims td{};
         td.N = N; td.nb = static_cast<int>(p.nb); td.B = p.B; td.Rp = Rp;
-        set_spmm_geometry(td, p, 1);
+        set_spmm_geometry(td, p);
         DevBuf<c128> part(static_cast<size_t>(td.Gs) * Rp);
         launch_spmm_seed<double>(st, p, td, p.S.get(), p.H.get(), xp.get(), yp.get(), dz.get(), dseed.get(),
                                  nullptr, part.get());

@@ -153,20 +153,6 @@ struct Ctx {
     Profiler prof;
 };
 
-// Clusters of C consecutive block rows that share one sorted union of their
-// column blocks: ptr[c]..ptr[c+1] index the union (col), blk[u*C + i] is the
-// stored block of (row c*C + i, col[u]) or -1.
-struct Clusters {
-    int C = 0;
-    int nc = 0;
-    DevBuf<int32_t> ptr, col, blk;
-    // packed walk for the Chebyshev step: pack[u] = col[u] | (row mask << 24),
-    // the mask's bit i set when row c*C + i stores a block in column col[u];
-    // perm lists the stored blocks in walk order (u, then i) and sptr[c] is
-    // cluster c's first position in perm (empty when nb >= 2^24)
-    DevBuf<int32_t> pack, perm, sptr;
-};
-
 struct Pair {
     Ctx *ctx = nullptr;
     int B = 4;
@@ -175,7 +161,6 @@ struct Pair {
     DevBuf<int32_t> colidx;     // nnzb
     DevBuf<int32_t> brow;       // nnzb: block row of every stored block
     DevBuf<int32_t> mirror;     // nnzb: index of the stored block (J, I)
-    Clusters cl;                // register-blocked product layout
     DevBuf<double> H, S;        // nnzb*B*B, FP64
     DevBuf<float> H32, S32;     // FP32 copies for mixed precision products
     bool f32_valid = false;

@@ -64,8 +64,6 @@ struct TileDims {
     int Lr;                   // rows per group (vector kernels)
     int Gs;                   // row groups of the SpMM kernels (multiple of 8); group g, wave w
                               // takes block rows 4g + w + 4 Gs i, i = 0, 1, ...
-    int variant = 1;          // SpMM kernel: 0 one block row per wave, 1 register-blocked clusters,
-                              // 2 slabs, 3 split-orbital 32-column stripes (Chebyshev step)
     bool nt = false;          // streamed vectors of the Chebyshev step bypass L2 retention
     int cb = 0;               // columns per Chebyshev column block (multiple of 64; Rp: one block)
 };

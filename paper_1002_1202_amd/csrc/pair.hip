@@ -9,75 +9,6 @@
 namespace gsc {
 
 // ------------------------------------------------------------------ pattern
-// Union of the column blocks of C consecutive block rows (host, once per
-// pattern).  One wave then loads each x block of the union once for all C
-// rows instead of once per row.
-void build_clusters(Pair &p, int C) {
-    const int64_t nb = p.nb;
-    const int nc = static_cast<int>((nb + C - 1) / C);
-    std::vector<int32_t> ptr(nc + 1, 0), col, blk;
-    col.reserve(p.nnzb);
-    blk.reserve(static_cast<size_t>(p.nnzb) * C);
-    std::vector<int32_t> cur(C);
-    for (int c = 0; c < nc; ++c) {
-        const int64_t r0 = static_cast<int64_t>(c) * C;
-        for (int i = 0; i < C; ++i) cur[i] = r0 + i < nb ? static_cast<int32_t>(p.h_rowptr[r0 + i]) : 0;
-        while (true) {
-            int32_t J = -1;
-            for (int i = 0; i < C; ++i) {
-                const int64_t r = r0 + i;
-                if (r < nb && cur[i] < p.h_rowptr[r + 1]) {
-                    const int32_t j = p.h_colidx[cur[i]];
-                    if (J < 0 || j < J) J = j;
-                }
-            }
-            if (J < 0) break;
-            col.push_back(J);
-            for (int i = 0; i < C; ++i) {
-                const int64_t r = r0 + i;
-                if (r < nb && cur[i] < p.h_rowptr[r + 1] && p.h_colidx[cur[i]] == J) blk.push_back(cur[i]++);
-                else blk.push_back(-1);
-            }
-        }
-        ptr[c + 1] = static_cast<int32_t>(col.size());
-    }
-    hipStream_t st = p.ctx->stream;
-    p.cl.C = C;
-    p.cl.nc = nc;
-    p.cl.ptr.alloc(ptr.size());
-    p.cl.col.alloc(col.size());
-    p.cl.blk.alloc(blk.size());
-    GSC_HIP(hipMemcpyAsync(p.cl.ptr.get(), ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, st));
-    GSC_HIP(hipMemcpyAsync(p.cl.col.get(), col.data(), col.size() * 4, hipMemcpyHostToDevice, st));
-    GSC_HIP(hipMemcpyAsync(p.cl.blk.get(), blk.data(), blk.size() * 4, hipMemcpyHostToDevice, st));
-    if (nb < (int64_t{1} << 24) && C <= 8) {
-        std::vector<int32_t> pack(col.size()), perm, sptr(nc + 1, 0);
-        perm.reserve(p.nnzb);
-        for (int c = 0; c < nc; ++c) {
-            sptr[c] = static_cast<int32_t>(perm.size());
-            for (int32_t u = ptr[c]; u < ptr[c + 1]; ++u) {
-                uint32_t mask = 0;
-                for (int i = 0; i < C; ++i) {
-                    const int32_t b = blk[static_cast<size_t>(u) * C + i];
-                    if (b >= 0) {
-                        mask |= 1u << i;
-                        perm.push_back(b);
-                    }
-                }
-                pack[u] = static_cast<int32_t>(static_cast<uint32_t>(col[u]) | (mask << 24));
-            }
-        }
-        sptr[nc] = static_cast<int32_t>(perm.size());
-        p.cl.pack.alloc(pack.size());
-        p.cl.perm.alloc(perm.size());
-        p.cl.sptr.alloc(sptr.size());
-        GSC_HIP(hipMemcpyAsync(p.cl.pack.get(), pack.data(), pack.size() * 4, hipMemcpyHostToDevice, st));
-        GSC_HIP(hipMemcpyAsync(p.cl.perm.get(), perm.data(), perm.size() * 4, hipMemcpyHostToDevice, st));
-        GSC_HIP(hipMemcpyAsync(p.cl.sptr.get(), sptr.data(), sptr.size() * 4, hipMemcpyHostToDevice, st));
-    }
-    GSC_HIP(hipStreamSynchronize(st));
-}
-
 void validate_and_upload(Pair &p, int block, int64_t nbrows, const int64_t *rowptr, const int32_t *colidx) {
     GSC_REQUIRE(block == 4 || block == 6, "block size must be 4 or 6");
     GSC_REQUIRE(nbrows > 0, "nbrows must be positive");
@@ -127,7 +58,6 @@ void validate_and_upload(Pair &p, int block, int64_t nbrows, const int64_t *rowp
     const size_t nv = static_cast<size_t>(nnzb) * block * block;
     p.H.alloc(nv);
     p.S.alloc(nv);
-    build_clusters(p, block == 4 ? 8 : 4);
     GSC_HIP(hipStreamSynchronize(st));
 }
 

@@ -1299,7 +1299,6 @@ int pick_groups(int64_t rows, int colchunks, int target_blocks) {
 template <typename T> struct Tile {
     TileDims td{};
     DevBuf<cpx<T>> p, q, r, res, d, w, ring, ringT;
-    DevBuf<T> scl;            // S blocks in cluster walk order (cluster Chebyshev step)
     DevBuf<cpx<T>> Xown, P;
     cpx<T> *X = nullptr;
     size_t ldk = 0;
@@ -1378,8 +1377,6 @@ template <typename T> class TileSolver {
         td.G = pick_groups(td.N, Rp / 64, 2048);
         td.Lr = div_up(td.N, td.G);
         {
-            const int k = req.opts.spmm_kernel;
-            const int variant = k == 2 ? 1 : k == 3 ? 2 : k == 4 ? 3 : 0;
             // columns per Chebyshev launch: all steps of the inner solve run
             // on one column block at a time, sized so that the three vectors
             // the step streams (y_k, y_{k-1}, r) stay in the 256 MB infinity
@@ -1388,8 +1385,8 @@ template <typename T> class TileSolver {
             const int cb = req.opts.cheb_block > 0
                                ? req.opts.cheb_block
                                : static_cast<int>(kChebBlockBytes / (3.0 * td.N * sizeof(cpx<T>))) / 64 * 64;
-            td.cb = (variant == 0 && cb >= (req.opts.cheb_block > 0 ? 64 : 128) && cb < Rp) ? cb : Rp;
-            set_spmm_geometry(td, pr_, variant);
+            td.cb = (cb >= (req.opts.cheb_block > 0 ? 64 : 128) && cb < Rp) ? cb : Rp;
+            set_spmm_geometry(td, pr_);
             td.nt = req.opts.stream_hint == 2;
         }
         st_ = ctx_.stream;
@@ -1478,11 +1475,6 @@ template <typename T> class TileSolver {
         const dim3 eg(td.Rp / 64, td.G), eb(kBlock);
         const int cb = div_up(td.Rp, 256);
         const size_t NR = static_cast<size_t>(td.N) * td.Rp;
-        if (td.variant == 1) {
-            const size_t nv = static_cast<size_t>(pr_.nnzb) * pr_.B * pr_.B;
-            if (t_.scl.n != nv) t_.scl.alloc(nv);
-            launch_permute_blocks<T>(st_, pr_, sval(), t_.scl.get());
-        }
         k_init_cols<<<cb, 256, 0, st_>>>(td.R, td.Rp, seed0, cs);
         k_init_shifts<<<div_up(static_cast<int64_t>(td.K) * td.Rp, 256), 256, 0, st_>>>(td.K, td.R, td.Rp, ss);
         if (t_.h.get()) GSC_HIP(hipMemsetAsync(t_.h.get(), 0, t_.h.n * sizeof(c128), st_));
@@ -1965,8 +1957,7 @@ template <typename T> class TileSolver {
     // so two buffers alternate.
     bool inner_solve_cheb(const gsc_opts &o, ColState cs, cpx<T> *ytarget, c128 *dot_part = nullptr) {
         (void)o;
-        // the fused y^T r needs the row layout (td.variant 0)
-        const bool dot = dot_part != nullptr && td_variant_row();
+        const bool dot = dot_part != nullptr;
         auto &td = t_.td;
         const T *Sv = sval();
         const double sigma = cheb_theta_ / cheb_delta_;
@@ -1979,11 +1970,7 @@ template <typename T> class TileSolver {
             const double rho = 1.0 / (2.0 * sigma - rho_prev);
             const double c1 = rho * rho_prev, c2 = 2.0 * rho / cheb_delta_;
             const int mode = kk == 1 ? 0 : kk == 2 ? 1 : 2;
-            if (td.variant == 1)
-                launch_cheb_cl<T>(st_, pr_, td, mode, t_.scl.get(), buf[kk % 2], t_.r.get(), buf[(kk + 1) % 2], skip,
-                                  1.0 / cheb_theta_, c1, c2, t_.part_d.get());
-            else
-                launch_cheb_step<T>(st_, pr_, td, mode, c0, w, Sv, buf[kk % 2], t_.r.get(), buf[(kk + 1) % 2],
+            launch_cheb_step<T>(st_, pr_, td, mode, c0, w, Sv, buf[kk % 2], t_.r.get(), buf[(kk + 1) % 2],
                                     skip, 1.0 / cheb_theta_, c1, c2, t_.part_d.get(), dot ? dot_part : nullptr,
                                     dot ? dot_mode : 0);
             rho_prev = rho;
@@ -2014,7 +2001,6 @@ template <typename T> class TileSolver {
         inner_total_ += K - 1;
         return dot;
     }
-    bool td_variant_row() const { return t_.td.variant == 0; }
 
     void inner_solve_cg(const gsc_opts &o, ColState cs, cpx<T> *y) {
         auto &td = t_.td;
@@ -2394,13 +2380,16 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
         }
     } catch (...) {
         ctx.prof.on = prof_was_on;
+        // other jobs' graphs and their status copies may still be in
+        // flight: drain every stream before anything they use is released
+        for (auto &st : streams) (void)hipStreamSynchronize(st);
         for (auto &L : live) {
             if (L.exec) (void)hipGraphExecDestroy(L.exec);
             if (L.graph) (void)hipGraphDestroy(L.graph);
             if (L.ev) (void)hipEventDestroy(L.ev);
             if (L.hstat) (void)hipHostFree(L.hstat);
         }
-        for (auto &st : streams) { (void)hipStreamSynchronize(st); (void)hipStreamDestroy(st); }
+        for (auto &st : streams) (void)hipStreamDestroy(st);
         throw;
     }
     ctx.prof.on = prof_was_on;

@@ -164,159 +164,6 @@ __global__ __launch_bounds__(kBlock) void k_spmm_S(
     }
 }
 
-// ------------------------------------------------------------------ cluster variants
-// One wave owns 64 columns and a cluster of C consecutive block rows; it
-// walks the sorted union of the cluster's column blocks, loads each x block
-// once and applies it to every row of the cluster that stores that block
-// (register blocking: C*B complex accumulators per lane).
-
-// q = zs_c * (S p) - H p with the complex coefficient (zs s - h) per entry;
-// partial sum_i p_i q_i.
-template <typename T, int B, int C>
-__global__ __launch_bounds__(kBlock) void k_spmm_seed_cl(
-    int nb, int nc, int Rp, int Lc, const int32_t *__restrict__ cptr, const int32_t *__restrict__ ccol,
-    const int32_t *__restrict__ cblk, const T *__restrict__ Sv, const T *__restrict__ Hv,
-    const cpx<T> *__restrict__ p, cpx<T> *__restrict__ q, const c128 *__restrict__ z,
-    const int *__restrict__ seed, const int *__restrict__ skip, c128 *__restrict__ partial) {
-    int cx, g;
-    xcd_remap(cx, g);
-    const int lane = threadIdx.x & 63;
-    const int w = wave_id();
-    const int col = cx * 64 + lane;
-    const bool act = skip == nullptr || !skip[col];
-    const c128 zs = act ? z[seed[col]] : c128{0, 0};
-    const T zr = static_cast<T>(zs.re), zi = static_cast<T>(zs.im);
-    c128 dot{0.0, 0.0};
-    const int c0 = g * Lc;
-    const int c1 = min(nc, c0 + Lc);
-    if (__ballot(act) != 0) {
-        for (int cl = c0 + w; cl < c1; cl += kWavesPerBlock) {
-            cpx<T> acc[C][B];
-#pragma unroll
-            for (int i = 0; i < C; ++i)
-#pragma unroll
-                for (int a = 0; a < B; ++a) acc[i][a] = {0, 0};
-            const int u0 = cptr[cl], u1 = cptr[cl + 1];
-            for (int u = u0; u < u1; ++u) {
-                const int J = ccol[u];
-                cpx<T> x[B];
-#pragma unroll
-                for (int c = 0; c < B; ++c)
-                    x[c] = p[static_cast<size_t>(J * B + c) * Rp + col];
-#pragma unroll
-                for (int i = 0; i < C; ++i) {
-                    const int b = cblk[u * C + i];
-                    if (b < 0) continue;
-                    const T *sb = Sv + static_cast<size_t>(b) * B * B;
-                    const T *hb = Hv + static_cast<size_t>(b) * B * B;
-#pragma unroll
-                    for (int a = 0; a < B; ++a) {
-#pragma unroll
-                        for (int c = 0; c < B; ++c) {
-                            const T sv = sb[a * B + c], hv = hb[a * B + c];
-                            const T cr = fma(zr, sv, -hv), ci = zi * sv;
-                            acc[i][a].re = fma(cr, x[c].re, fma(-ci, x[c].im, acc[i][a].re));
-                            acc[i][a].im = fma(cr, x[c].im, fma(ci, x[c].re, acc[i][a].im));
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < C; ++i) {
-                const int I = cl * C + i;
-                if (I < nb && act) {
-#pragma unroll
-                    for (int a = 0; a < B; ++a) {
-                        const size_t e = static_cast<size_t>(I * B + a) * Rp + col;
-                        q[e] = acc[i][a];
-                        dot = dot + ccast<double>(p[e]) * ccast<double>(acc[i][a]);
-                    }
-                }
-            }
-        }
-    }
-    __shared__ c128 red[kWavesPerBlock][64];
-    red[w][lane] = dot;
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        c128 s = red[0][lane];
-#pragma unroll
-        for (int k = 1; k < kWavesPerBlock; ++k) s = s + red[k][lane];
-        partial[static_cast<size_t>(g) * Rp + col] = s;
-    }
-}
-
-// w = S d, partial Re(d^H S d)
-template <typename T, int B, int C>
-__global__ __launch_bounds__(kBlock) void k_spmm_S_cl(
-    int nb, int nc, int Rp, int Lc, const int32_t *__restrict__ cptr, const int32_t *__restrict__ ccol,
-    const int32_t *__restrict__ cblk, const T *__restrict__ Sv, const cpx<T> *__restrict__ d,
-    cpx<T> *__restrict__ wout, const int *__restrict__ skip, double *__restrict__ partial) {
-    int cx, g;
-    xcd_remap(cx, g);
-    const int lane = threadIdx.x & 63;
-    const int wv = wave_id();
-    const int col = cx * 64 + lane;
-    const bool act = !skip[col];
-    double dot = 0.0;
-    const int c0 = g * Lc;
-    const int c1 = min(nc, c0 + Lc);
-    if (__ballot(act) != 0) {
-        for (int cl = c0 + wv; cl < c1; cl += kWavesPerBlock) {
-            cpx<T> acc[C][B];
-#pragma unroll
-            for (int i = 0; i < C; ++i)
-#pragma unroll
-                for (int a = 0; a < B; ++a) acc[i][a] = {0, 0};
-            const int u0 = cptr[cl], u1 = cptr[cl + 1];
-            for (int u = u0; u < u1; ++u) {
-                const int J = ccol[u];
-                cpx<T> x[B];
-#pragma unroll
-                for (int c = 0; c < B; ++c)
-                    x[c] = d[static_cast<size_t>(J * B + c) * Rp + col];
-#pragma unroll
-                for (int i = 0; i < C; ++i) {
-                    const int b = cblk[u * C + i];
-                    if (b < 0) continue;
-                    const T *sb = Sv + static_cast<size_t>(b) * B * B;
-#pragma unroll
-                    for (int a = 0; a < B; ++a) {
-#pragma unroll
-                        for (int c = 0; c < B; ++c) {
-                            const T sv = sb[a * B + c];
-                            acc[i][a].re = fma(sv, x[c].re, acc[i][a].re);
-                            acc[i][a].im = fma(sv, x[c].im, acc[i][a].im);
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < C; ++i) {
-                const int I = cl * C + i;
-                if (I < nb && act) {
-#pragma unroll
-                    for (int a = 0; a < B; ++a) {
-                        const size_t e = static_cast<size_t>(I * B + a) * Rp + col;
-                        wout[e] = acc[i][a];
-                        const cpx<T> own = d[e];
-                        dot += static_cast<double>(own.re) * acc[i][a].re + static_cast<double>(own.im) * acc[i][a].im;
-                    }
-                }
-            }
-        }
-    }
-    __shared__ double red[kWavesPerBlock][64];
-    red[wv][lane] = dot;
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        double s = red[0][lane];
-#pragma unroll
-        for (int k = 1; k < kWavesPerBlock; ++k) s += red[k][lane];
-        partial[static_cast<size_t>(g) * Rp + col] = s;
-    }
-}
-
 // ------------------------------------------------------------------ Chebyshev step
 // One step of the Chebyshev iteration for S y = r on the interval
 // [theta - delta, theta + delta] fused with the product, in the three-term
@@ -416,17 +263,7 @@ void launch_cheb_step(hipStream_t st, const Pair &pr, const TileDims &td, int mo
                       double inv_theta, double c1, double c2, double *partial, c128 *dpart, int dot_mode) {
     GSC_REQUIRE(col0 % 64 == 0 && ncols % 64 == 0 && ncols > 0 && col0 + ncols <= td.Rp,
                 "Chebyshev column block outside the tile");
-    GSC_REQUIRE(td.variant == 0 || (col0 == 0 && ncols == td.Rp), "column blocks need the row layout");
-    GSC_REQUIRE(dot_mode == 0 || (td.variant == 0 && dpart != nullptr), "the fused dot needs the row layout");
-    if (td.variant == 2) {
-        launch_cheb_slab<T>(st, pr, td, mode, Sv, y, r, yio, skip, inv_theta, c1, c2, partial);
-        return;
-    }
-    if (td.variant == 3) {
-        launch_cheb_split<T>(st, pr, td, mode, Sv, y, r, yio, skip, inv_theta, c1, c2, partial);
-        return;
-    }
-    // the fused step uses the row layout (one block row per wave and step)
+    GSC_REQUIRE(dot_mode == 0 || dpart != nullptr, "the fused dot needs its partials");
     dim3 grid(ncols / 64, td.Gs), block(kBlock);
     const T it = static_cast<T>(inv_theta), a = static_cast<T>(c1), b = static_cast<T>(c2);
 #define GSC_CHEB_D(BB, M, N, D)                                                                                   \
@@ -454,64 +291,26 @@ template void launch_cheb_step<float>(hipStream_t, const Pair &, const TileDims 
                                       double *, c128 *, int);
 
 // ------------------------------------------------------------------ launchers
-// Row-group geometry of the product kernels.  Every reduction of their
-// partials uses td.Gs, so both variants launch exactly td.Gs row groups.
-void set_spmm_geometry(TileDims &td, const Pair &pr, int variant) {
-    td.variant = variant;
-    if (variant == 2) {
-        // slab kernels: one block row per wave, 4 per workgroup
-        td.Gs = slab_groups(td.nb);
-        return;
-    }
-    if (variant == 1) {
-        // one cluster per wave: 4 clusters per block of 4 waves
-        td.Gs = (div_up(pr.cl.nc, kWavesPerBlock) + 7) / 8 * 8;
-    } else if (variant == 3) {
-        // 32-column stripes: about 16k waves over the stripes and row groups
-        int g = std::max(1, 4096 / std::max(1, td.Rp / 32));
-        g = static_cast<int>(std::min<int64_t>(g, (td.nb + 3) / 4));
-        td.Gs = (std::max(g, 1) + 7) / 8 * 8;
-    } else {
-        // one block row per wave where the rows allow: the rows a sweep
-        // keeps in flight then span few x-planes, whose halo fits L2.  With
-        // more than 8 column chunks an XCD would run the row groups of
-        // several chunks at once (each with its own x window) unless the
-        // groups of one chunk fill it: at least 256 groups then.
-        const int w = td.cb > 0 && td.cb < td.Rp ? td.cb : td.Rp;   // width of a Chebyshev launch
-        int g = std::max(1, 4096 / std::max(1, w / 64));
-        if (w / 64 > 8) g = std::max(g, 256);
-        g = static_cast<int>(std::min<int64_t>(g, (td.nb + 3) / 4));
-        td.Gs = (std::max(g, 1) + 7) / 8 * 8;
-    }
+// Row-group geometry of the product kernels (td.Gs row groups; every
+// reduction of their partials uses td.Gs).  One block row per wave where the
+// rows allow: the rows a sweep keeps in flight then span few x-planes, whose
+// halo fits L2.  With more than 8 column chunks an XCD would run the row
+// groups of several chunks at once (each with its own x window) unless the
+// groups of one chunk fill it: at least 256 groups then.
+void set_spmm_geometry(TileDims &td, const Pair &pr) {
+    (void)pr;
+    const int w = td.cb > 0 && td.cb < td.Rp ? td.cb : td.Rp;   // width of a Chebyshev launch
+    int g = std::max(1, 4096 / std::max(1, w / 64));
+    if (w / 64 > 8) g = std::max(g, 256);
+    g = static_cast<int>(std::min<int64_t>(g, (td.nb + 3) / 4));
+    td.Gs = (std::max(g, 1) + 7) / 8 * 8;
 }
 
-inline void cluster_geometry(const Pair &pr, const TileDims &td, int &gy, int &Lc) {
-    gy = td.Gs;
-    Lc = div_up(pr.cl.nc, td.Gs);
-}
 template <typename T>
 void launch_spmm_seed(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const T *Hv,
                       const cpx<T> *p, cpx<T> *q, const c128 *z, const int *seed, const int *skip,
                       c128 *partial) {
     dim3 grid(td.Rp / 64, td.Gs), block(kBlock);
-    if (td.variant == 2) {
-        launch_spmm_seed_slab<T>(st, pr, td, Sv, Hv, p, q, z, seed, skip, partial);
-        return;
-    }
-    if (td.variant == 1) {
-        int gy, Lc;
-        cluster_geometry(pr, td, gy, Lc);
-        if (pr.B == 4)
-            k_spmm_seed_cl<T, 4, 8><<<grid, block, 0, st>>>(td.nb, pr.cl.nc, td.Rp, Lc, pr.cl.ptr.get(),
-                                                            pr.cl.col.get(), pr.cl.blk.get(), Sv, Hv, p, q, z,
-                                                            seed, skip, partial);
-        else
-            k_spmm_seed_cl<T, 6, 4><<<grid, block, 0, st>>>(td.nb, pr.cl.nc, td.Rp, Lc, pr.cl.ptr.get(),
-                                                            pr.cl.col.get(), pr.cl.blk.get(), Sv, Hv, p, q, z,
-                                                            seed, skip, partial);
-        GSC_HIP(hipGetLastError());
-        return;
-    }
     if (pr.B == 4)
         k_spmm_seed<T, 4><<<grid, block, 0, st>>>(td.nb, td.Rp, pr.rowptr.get(), pr.colidx.get(),
                                                   Sv, Hv, p, q, z, seed, skip, partial);
@@ -525,22 +324,6 @@ template <typename T>
 void launch_spmm_S(hipStream_t st, const Pair &pr, const TileDims &td, const T *Sv, const cpx<T> *d,
                    cpx<T> *w, const int *skip, double *partial) {
     dim3 grid(td.Rp / 64, td.Gs), block(kBlock);
-    if (td.variant == 2) {
-        launch_spmm_S_slab<T>(st, pr, td, Sv, d, w, skip, partial);
-        return;
-    }
-    if (td.variant == 1) {
-        int gy, Lc;
-        cluster_geometry(pr, td, gy, Lc);
-        if (pr.B == 4)
-            k_spmm_S_cl<T, 4, 8><<<grid, block, 0, st>>>(td.nb, pr.cl.nc, td.Rp, Lc, pr.cl.ptr.get(),
-                                                         pr.cl.col.get(), pr.cl.blk.get(), Sv, d, w, skip, partial);
-        else
-            k_spmm_S_cl<T, 6, 4><<<grid, block, 0, st>>>(td.nb, pr.cl.nc, td.Rp, Lc, pr.cl.ptr.get(),
-                                                         pr.cl.col.get(), pr.cl.blk.get(), Sv, d, w, skip, partial);
-        GSC_HIP(hipGetLastError());
-        return;
-    }
     if (pr.B == 4)
         k_spmm_S<T, 4><<<grid, block, 0, st>>>(td.nb, td.Rp, pr.rowptr.get(), pr.colidx.get(), Sv,
                                                d, w, skip, partial);

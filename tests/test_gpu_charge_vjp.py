@@ -101,3 +101,30 @@ def test_autograd_charge_loss_forces(ctx):
             vals.append(float(cvec @ qq))
         fd = -(vals[0] - vals[1]) / (2 * h)
         assert fd == pytest.approx(F[atom, ax], rel=1e-5, abs=1e-7)
+
+
+def test_autograd_charges_backward_after_another_forward(ctx):
+    """The backward of the charges uses the H, S of its own forward even when
+    another forward at other positions ran on the same pair in between."""
+    import torch
+    from paper_1002_1202_amd import api, autograd
+    c = configs.water_small(n_mol=6, n_rhs=4, n_shift=10, eta=0.3)
+    s, z = c["system"], c["z"]
+    print("case: charges backward after a second forward", flush=True)
+    w = np.full(len(z), 0.4)
+    orbs = np.array([1, 7, 18, 30])
+    cvec = np.array([0.7, -1.1, 0.4, 1.5])
+    pair, scale = api.pair_from_system(ctx, s)
+    pos = torch.tensor(s.positions, dtype=torch.float64, requires_grad=True)
+    q = autograd.mulliken_charges(ctx, pair, s, pos, z, w, orbs, scale, tol=1e-12)
+    moved = s.positions.copy()
+    moved[2] += np.array([0.3, -0.2, 0.1])
+    pos2 = torch.tensor(moved, dtype=torch.float64, requires_grad=True)
+    autograd.mulliken_charges(ctx, pair, s, pos2, z, w, orbs, scale, tol=1e-12)
+    (q * torch.from_numpy(cvec).to(q.device)).sum().backward()
+    F = -pos.grad.numpy()
+    S, H, _ = oased.dense_pair(s, c=scale)
+    gH, gS = ogreen.charge_grad_dense(H, S, z, w, orbs, cvec)
+    F0 = oased.forces(s, oased.gather_blocks(s, gH), oased.gather_blocks(s, gS), scale)
+    print(f"  |F - F0| / |F0| = {rel(F, F0):.2e}", flush=True)
+    assert rel(F, F0) < 1e-8

@@ -268,20 +268,6 @@ def test_ased_vjp_matches_oracle(ctx, si216):
     assert rel(F, F0) < 1e-12
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
-def test_spmm_variants_in_solve(ctx, si216, kernel):
-    """Both product kernels (one block row per wave; register-blocked
-    clusters of block rows) give the LU solution."""
-    from paper_1002_1202_amd import api
-    c, S, H, _ = si216
-    print(f"case: spmm_kernel={kernel}", flush=True)
-    pair, _ = api.pair_from_system(ctx, c["system"])
-    rhs = c["rhs"][:12]
-    res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, spmm_kernel=kernel)
-    X = ogreen.solve_dense(H, S, c["z"], rhs)
-    assert rel(res.G_cols, X) < 1e-10
-
-
 @pytest.mark.parametrize("method", [1, 2])
 def test_inner_methods(ctx, si216, method):
     """Inner S-solve by CG (1) or by the Chebyshev iteration on the Ritz
@@ -314,11 +300,11 @@ def test_chebyshev_projected_water(ctx):
 
 
 @pytest.mark.parametrize("carry", ["full", "projected"])
-def test_slab_kernel_water_and_si(ctx, si216, carry):
-    """The slab product layout (16 rhs per wave for B = 4, 10 for B = 6) with
-    a ragged tail of columns, both carries."""
+def test_ragged_tail_water_and_si(ctx, si216, carry):
+    """B = 4 and B = 6 with a ragged tail of columns (70 rhs -> a second,
+    partly padded 64-column chunk), both carries."""
     from paper_1002_1202_amd import api
-    print(f"case: slab kernels carry={carry}", flush=True)
+    print(f"case: ragged tail carry={carry}", flush=True)
     for c in (si216[0], configs.water_small(n_mol=40, n_rhs=23)):
         s = c["system"]
         S, H, _ = oased.dense_pair(s)
@@ -326,19 +312,17 @@ def test_slab_kernel_water_and_si(ctx, si216, carry):
         rhs = c["rhs"][:70]
         X = ogreen.solve_dense(H, S, c["z"], rhs)
         if carry == "full":
-            res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, spmm_kernel=3)
+            res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12)
             assert rel(res.G_cols, X) < 1e-10
         else:
             proj = rhs[:, None]
-            res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, spmm_kernel=3, carry="projected", proj=proj)
+            res = api.solve(ctx, pair, c["z"], rhs=rhs, tol=1e-12, carry="projected", proj=proj)
             assert rel(res.G_proj[:, :, 0], X[:, np.arange(len(rhs)), rhs]) < 1e-10
 
 
-@pytest.mark.parametrize("kernel,hint", [(4, 1), (4, 2), (2, 1)])
+@pytest.mark.parametrize("kernel,hint", [(1, 2)])
 def test_chebyshev_kernel_variants(ctx, si216, kernel, hint):
-    """The Chebyshev step of the other product layouts: 32-column stripes
-    with the block's orbitals split over the two half-waves (kernel 4, both
-    cache policies for the streamed vectors) and the cluster walk (kernel 2),
+    """The Chebyshev step with nontemporal streamed vectors (stream_hint 2),
     B = 4 and B = 6, a ragged column tail (70 rhs -> 2 tiles of 64), FP64
     and complex64 products."""
     from paper_1002_1202_amd import api
