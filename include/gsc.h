@@ -56,7 +56,7 @@ typedef enum {
     GSC_E_UNSUPPORTED = -7
 } gsc_status;
 
-typedef enum { GSC_FP64 = 0, GSC_MIXED = 1 } gsc_precision;
+typedef enum { GSC_FP64 = 0, GSC_MIXED = 1, GSC_C64 = 2 } gsc_precision;
 typedef enum { GSC_CARRY_FULL = 0, GSC_CARRY_PROJECTED = 1 } gsc_carry;
 typedef enum { GSC_MEM_HOST = 0, GSC_MEM_DEVICE = 1 } gsc_mem;
 
@@ -72,8 +72,17 @@ typedef struct {
     double inner_tol;      /* [0 = max(1e-2 tol, 1e-15)] relative residual of
                               the inner CG for S r' = r                        */
     int inner_max_iter;    /* [200]                                            */
-    int precision;         /* [GSC_FP64] GSC_MIXED: complex64 vectors and
-                              products, FP64 scalars, dots and reductions      */
+    int precision;         /* [GSC_FP64] GSC_MIXED: the seed process (products
+                              with H and S, seed vectors, dots, recurrences)
+                              stays FP64 and the inner S-solve runs complex64
+                              Chebyshev rounds (FP32 S and arithmetic) refined
+                              by FP64 residuals to the same inner tolerance,
+                              so results keep the FP64 accuracy (needs the
+                              Chebyshev inner solve; with CG it is FP64).
+                              GSC_C64: complex64 vectors and products for the
+                              whole seed process, FP64 scalars and dots; its
+                              accuracy is limited to about cond(z S - H) times
+                              the FP32 epsilon, not by tol                     */
     int carry;             /* [GSC_CARRY_FULL] keep x^k, p^k as full vectors;
                               GSC_CARRY_PROJECTED keeps c^T x^k only and
                               replaces seed switching by a collinear restart   */
@@ -110,7 +119,7 @@ typedef struct {
                               anew when its step count changes): each outer
                               iteration solves S r' = r to inner_tol divided
                               by the largest residual among the shifts still
-                              above tol (at most 1e-6, at least inner_tol),
+                              above tol (at most 1e-4, at least inner_tol),
                               so the inner error that reaches every
                               unconverged shift stays at inner_tol relative
                               to ||b||.  0 keeps the fixed inner_tol of the
@@ -131,6 +140,12 @@ typedef struct {
     double *res_recursive;        /* [k][r] ||r_n|| / (|pi| ||b||) at exit      */
     double *res_true;             /* [k][r] FP64 ||b - A_k x_k|| / ||b||        */
     unsigned char *converged;     /* [k][r] 1 if res_recursive <= tol          */
+    double alg_bytes;             /* gsc_solve_batched: algorithmic HBM bytes
+                                     of the outer iterations (every vector
+                                     element read or written once, each
+                                     matrix once per product launch; gathers'
+                                     re-reads excluded), 0 elsewhere         */
+    double alg_bytes_inner;       /* the inner S-solve's share of alg_bytes   */
 } gsc_stats;
 
 /* ASED geometry for gsc_ased_build / gsc_ased_vjp (Sec. 2.2, eq. Hap-1).
@@ -357,8 +372,10 @@ gsc_status gsc_band_energy_vjp(gsc_ctx *ctx, const gsc_pair *pair, int nshift, c
  * gsc_profile_enable(ctx, 1) resets the counters and turns timing on.
  * gsc_profile_read returns, for one kernel name ("spmm_seed", "spmm_S",
  * "shift_update", "cg_update", "cg_dir", "update_r", "rho_dot", "p_update",
- * "ctrl", "post", "proj_update", "cheb_step", "ring_transpose", and for the
- * generalised Lanczos process "lz_hprod", "lz_update", "lz_scale"), the summed
+ * "ctrl", "post", "proj_update", "cheb_step", "ring_transpose", the mixed
+ * inner solve's "cheb_mx" (complex64 steps) and "mx_resid" (FP64 residuals),
+ * and for the generalised Lanczos process "lz_hprod", "lz_update",
+ * "lz_scale"), the summed
  * device milliseconds, the number of launches and the summed algorithmic
  * bytes those launches must move (the method's own reads and writes, no re-reads).  GSC_E_ARG for an
  * unknown name. */

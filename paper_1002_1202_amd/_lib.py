@@ -12,7 +12,7 @@ GSC_OK, GSC_NOT_CONVERGED = 0, 1
 STATUS_NAMES = {0: "GSC_OK", 1: "GSC_NOT_CONVERGED", -1: "GSC_E_ARG", -2: "GSC_E_NOMEM",
                 -3: "GSC_E_DEVICE", -4: "GSC_E_BREAKDOWN", -5: "GSC_E_S_NOT_SPD",
                 -6: "GSC_E_NAN", -7: "GSC_E_UNSUPPORTED"}
-FP64, MIXED = 0, 1
+FP64, MIXED, C64 = 0, 1, 2
 CARRY_FULL, CARRY_PROJECTED = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 
@@ -30,7 +30,8 @@ class Stats(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("inner_iters", C.c_longlong), ("switches", C.c_int),
                 ("restarts", C.c_int), ("shift_rhs_iters", C.c_longlong), ("seconds", C.c_double),
                 ("res_recursive", C.POINTER(C.c_double)), ("res_true", C.POINTER(C.c_double)),
-                ("converged", C.POINTER(C.c_ubyte))]
+                ("converged", C.POINTER(C.c_ubyte)), ("alg_bytes", C.c_double),
+                ("alg_bytes_inner", C.c_double)]
 
 
 class AsedGeom(C.Structure):
@@ -97,7 +98,7 @@ SIGNATURES = {
 
 KERNELS = ("spmm_seed", "spmm_S", "shift_update", "cg_update", "cg_dir", "update_r", "rho_dot",
            "p_update", "ctrl", "post", "proj_update", "cheb_step", "ring_transpose", "lz_hprod",
-           "lz_update", "lz_scale")
+           "lz_update", "lz_scale", "cheb_mx", "mx_resid")
 
 _lib = None
 

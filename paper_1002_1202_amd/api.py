@@ -201,14 +201,17 @@ def make_opts(tol=1e-10, max_iter=5000, inner_tol=0.0, inner_max_iter=200, preci
               inner_relax=False) -> L.Opts:
     """gsc_opts with the library's defaults for every option not given (the
     fields and their meaning are those of gsc_opts in include/gsc.h).
-    ``precision``: "fp64" or "mixed" (complex64 products, FP64 recurrences);
+    ``precision``: "fp64"; "mixed" (FP64 seed process, inner S-solve in
+    complex64 rounds refined by FP64 residuals: FP64 accuracy); or "c64"
+    (complex64 vectors and products throughout, FP64 scalars and dots:
+    accuracy limited to about cond(z S - H) times the FP32 epsilon);
     ``carry``: "full" (every x^k) or "projected"; ``inner_relax``: relaxed
     inner tolerance (off by default: the fixed inner tolerance of the
     method)."""
     o = L.Opts()
     L.load().gsc_opts_default(C.byref(o))
     o.tol, o.max_iter, o.inner_tol, o.inner_max_iter = tol, max_iter, inner_tol, inner_max_iter
-    o.precision = {"fp64": L.FP64, "mixed": L.MIXED}[precision]
+    o.precision = {"fp64": L.FP64, "mixed": L.MIXED, "c64": L.C64}[precision]
     o.carry = {"full": L.CARRY_FULL, "projected": L.CARRY_PROJECTED}[carry]
     o.seed_index, o.fuse_steps, o.rhs_tile, o.recheck = seed_index, fuse_steps, rhs_tile, int(recheck)
     o.spmm_kernel = spmm_kernel
@@ -541,6 +544,7 @@ def solve_batched(ctx: Context, problems, **opt):
         st = o.pop("stats")
         o.update(status=status, outer_iters=st.outer_iters, inner_iters=st.inner_iters,
                  shift_rhs_iters=st.shift_rhs_iters, seconds=st.seconds,
+                 alg_bytes=st.alg_bytes, alg_bytes_inner=st.alg_bytes_inner,
                  converged=o["converged"].astype(bool))
     del keep
     return outs

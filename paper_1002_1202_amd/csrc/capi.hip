@@ -114,7 +114,7 @@ void validate_opts(const gsc_opts &o) {
     GSC_REQUIRE(o.tol > 0 && std::isfinite(o.tol), "tol must be positive");
     GSC_REQUIRE(o.max_iter > 0, "max_iter must be positive");
     GSC_REQUIRE(o.inner_max_iter > 0, "inner_max_iter must be positive");
-    GSC_REQUIRE(o.precision == GSC_FP64 || o.precision == GSC_MIXED, "unknown precision");
+    GSC_REQUIRE(o.precision == GSC_FP64 || o.precision == GSC_MIXED || o.precision == GSC_C64, "unknown precision");
     GSC_REQUIRE(o.carry == GSC_CARRY_FULL || o.carry == GSC_CARRY_PROJECTED, "unknown carry mode");
     GSC_REQUIRE(o.fuse_steps >= 0 && o.fuse_steps <= kMaxFuse, "fuse_steps must be in [0, 16]");
     GSC_REQUIRE(o.spmm_kernel >= 0 && o.spmm_kernel <= 1, "spmm_kernel must be 0 or 1");
@@ -964,6 +964,8 @@ gsc_status gsc_solve_batched(gsc_ctx *ctx, int nsys, const gsc_problem *problems
                 pb.stats->shift_rhs_iters = 0;
                 pb.stats->switches = 0;
                 pb.stats->restarts = 0;
+                pb.stats->alg_bytes = 0.0;
+                pb.stats->alg_bytes_inner = 0.0;
             }
         }
         hipEvent_t e0, e1;

@@ -114,7 +114,7 @@ template <typename T> struct DevBuf {
 enum KernelId : int {
     KP_SPMM_SEED = 0, KP_SPMM_S, KP_SHIFT_UPDATE, KP_CG_UPDATE, KP_CG_DIR, KP_UPDATE_R,
     KP_RHO_DOT, KP_P_UPDATE, KP_CTRL, KP_POST, KP_PROJ_UPDATE, KP_CHEB, KP_RING_T,
-    KP_LZ_HPROD, KP_LZ_UPDATE, KP_LZ_SCALE, KP_COUNT
+    KP_LZ_HPROD, KP_LZ_UPDATE, KP_LZ_SCALE, KP_CHEB_MX, KP_MX_RESID, KP_COUNT
 };
 const char *kernel_name(int id);
 

@@ -127,16 +127,17 @@ __device__ inline void st_cpx(cpx<T> v, cpx<T> *p) {
 }
 
 // Three-term Chebyshev update of one element of S y = r:
-//   res = r - S y_k,   y_{k+1} = y_k + c1 (y_k - y_{k-1}) + c2 res,
-// written over y_{k-1} (yio).  own = y_k at this element (taken from the
-// gathered diagonal block), Sx = the gathered product.  MODE 0: the first
-// step, whose gathered vector is r and y_1 = r / theta, y_0 = 0; MODE 1:
-// y_{k-1} = y_1 = r / theta is formed from r; MODE 2: y_{k-1} is read.
-// Returns |res|^2; with dacc, also adds y_{k+1} r (unconjugated, FP64) to it.
+//   res = r - S y_k,   y_{k+1} = y_k + c1 (y_k - y_{k-1}) + c2 res.
+// own = y_k at this element (taken from the gathered diagonal block), Sx =
+// the gathered product.  MODE 0: the first step, whose gathered vector is r
+// and y_1 = r / theta, y_0 = 0; MODE 1: y_{k-1} = y_1 = r / theta is formed
+// from r; MODE 2: y_{k-1} is read from yprev_src.  Returns y_{k+1}; res2 gets
+// |res|^2 and rv the element of r.
 template <typename T, int MODE, bool NT>
-__device__ inline double cheb_update(cpx<T> own, cpx<T> Sx, const cpx<T> *__restrict__ r, cpx<T> *__restrict__ yio,
-                                     size_t e, T inv_theta, T c1, T c2, c128 *dacc = nullptr) {
-    cpx<T> yk, rv, yprev, Sy = Sx;
+__device__ inline cpx<T> cheb_next(cpx<T> own, cpx<T> Sx, const cpx<T> *__restrict__ r,
+                                   const cpx<T> *__restrict__ yprev_src, size_t e, T inv_theta, T c1, T c2,
+                                   double &res2, cpx<T> &rv) {
+    cpx<T> yk, yprev, Sy = Sx;
     if constexpr (MODE == 0) {
         rv = own;
         yk = inv_theta * own;
@@ -146,13 +147,24 @@ __device__ inline double cheb_update(cpx<T> own, cpx<T> Sx, const cpx<T> *__rest
         rv = ld_cpx<T, NT>(r + e);
         yk = own;
         if constexpr (MODE == 1) yprev = inv_theta * rv;
-        else yprev = ld_cpx<T, NT>(yio + e);
+        else yprev = ld_cpx<T, NT>(yprev_src + e);
     }
     const cpx<T> res = rv - Sy;
-    const cpx<T> ynew = yk + c1 * (yk - yprev) + c2 * res;
+    res2 = static_cast<double>(res.re) * res.re + static_cast<double>(res.im) * res.im;
+    return yk + c1 * (yk - yprev) + c2 * res;
+}
+
+// The update above with y_{k+1} written over y_{k-1} (yio).  Returns |res|^2;
+// with dacc, also adds y_{k+1} r (unconjugated, FP64) to it.
+template <typename T, int MODE, bool NT>
+__device__ inline double cheb_update(cpx<T> own, cpx<T> Sx, const cpx<T> *__restrict__ r, cpx<T> *__restrict__ yio,
+                                     size_t e, T inv_theta, T c1, T c2, c128 *dacc = nullptr) {
+    double res2;
+    cpx<T> rv;
+    const cpx<T> ynew = cheb_next<T, MODE, NT>(own, Sx, r, yio, e, inv_theta, c1, c2, res2, rv);
     st_cpx<T, NT>(ynew, yio + e);
     if (dacc) *dacc = *dacc + ccast<double>(ynew) * ccast<double>(rv);
-    return static_cast<double>(res.re) * res.re + static_cast<double>(res.im) * res.im;
+    return res2;
 }
 
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }

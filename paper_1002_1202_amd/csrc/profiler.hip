@@ -7,7 +7,8 @@ const char *kernel_name(int id) {
     static const char *names[KP_COUNT] = {"spmm_seed", "spmm_S",  "shift_update", "cg_update",
                                           "cg_dir",    "update_r", "rho_dot",     "p_update",
                                           "ctrl",      "post",     "proj_update", "cheb_step",
-                                          "ring_transpose", "lz_hprod", "lz_update", "lz_scale"};
+                                          "ring_transpose", "lz_hprod", "lz_update", "lz_scale",
+                                          "cheb_mx",   "mx_resid"};
     return (id >= 0 && id < KP_COUNT) ? names[id] : "";
 }
 

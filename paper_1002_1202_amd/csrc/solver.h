@@ -9,6 +9,7 @@ struct Status {
     int switched;          // columns that switched seed (or restarted) this iteration
     int flags;             // OR of FLAG_* over columns
     double worst_res;      // largest shifted residual still above tol, over columns (-1: none)
+    long long col_iters;   // outer iterations summed over the columns so far
 };
 
 // Projections carried by the projected mode: M unit vectors c_m = e_i per

@@ -543,11 +543,18 @@ __global__ void k_copy_vec(size_t n, const cpx<T> *a, cpx<T> *b) {
     if (i < n) b[i] = a[i];
 }
 
+__global__ void k_to_c64(size_t n, const c128 *a, c64 *b) {
+    const size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = ccast<float>(a[i]);
+}
+
 __global__ void k_status(int Rp, ColState cs, Status *st) {
     __shared__ int a[kBlock], b[kBlock], s[kBlock], f[kBlock];
     __shared__ double wr[kBlock];
+    __shared__ long long it[kBlock];
     int na = 0, nb = 0, ns = 0, fl = 0;
     double w = -1.0;
+    long long ni = 0;
     for (int c = threadIdx.x; c < Rp; c += kBlock) {
         const int done = cs.done[c];
         na += !done;
@@ -555,8 +562,10 @@ __global__ void k_status(int Rp, ColState cs, Status *st) {
         ns += (!done && cs.sw[c] != 0);
         fl |= cs.flags[c];
         if (!done) w = fmax(w, cs.wres[c]);
+        ni += cs.iters[c];
     }
     a[threadIdx.x] = na; b[threadIdx.x] = nb; s[threadIdx.x] = ns; f[threadIdx.x] = fl; wr[threadIdx.x] = w;
+    it[threadIdx.x] = ni;
     __syncthreads();
     for (int k = kBlock / 2; k > 0; k >>= 1) {
         if (threadIdx.x < k) {
@@ -565,6 +574,7 @@ __global__ void k_status(int Rp, ColState cs, Status *st) {
             s[threadIdx.x] += s[threadIdx.x + k];
             f[threadIdx.x] |= f[threadIdx.x + k];
             wr[threadIdx.x] = fmax(wr[threadIdx.x], wr[threadIdx.x + k]);
+            it[threadIdx.x] += it[threadIdx.x + k];
         }
         __syncthreads();
     }
@@ -574,14 +584,18 @@ __global__ void k_status(int Rp, ColState cs, Status *st) {
         st->switched = s[0];
         st->flags = f[0];
         st->worst_res = wr[0];
+        st->col_iters = it[0];
     }
 }
 
 // ------------------------------------------------------------------ vector kernels
+// r <- r - alpha q; r32 (if given) receives r in complex64: the right-hand
+// side of the first complex64 round of the mixed inner solve
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_r(int N, int Rp, int Lr, const int *done,
                                                      const c128 *alpha, const cpx<T> *q, cpx<T> *r,
-                                                     cpx<T> *res, cpx<T> *d, double *partial, int copy) {
+                                                     cpx<T> *res, cpx<T> *d, double *partial, int copy,
+                                                     c64 *r32) {
     ELEM_LOOP_BEGIN
     double acc = 0.0;
     if (!done[col]) {
@@ -590,6 +604,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int N, int Rp, int Lr, cons
             const size_t e = static_cast<size_t>(i) * Rp + col;
             const cpx<T> v = r[e] - a * q[e];
             r[e] = v;
+            if (r32) r32[e] = ccast<float>(v);
             if (copy) {
                 // starting residual and direction of a CG inner solve
                 res[e] = v;
@@ -1390,6 +1405,7 @@ template <typename T> class TileSolver {
             td.nt = req.opts.stream_hint == 2;
         }
         st_ = ctx_.stream;
+        mixed_ = std::is_same<T, double>::value && req.opts.precision == GSC_MIXED;
         if (ctx_.prof.on) {
             const int mi = std::max(1, req.opts.max_iter);
             t_.act_hist.alloc(mi);
@@ -1405,6 +1421,7 @@ template <typename T> class TileSolver {
         t_.p.alloc(NR); t_.q.alloc(NR); t_.r.alloc(NR); t_.res.alloc(NR); t_.d.alloc(NR); t_.w.alloc(NR);
         t_.ring.alloc(NR * td.m);
         if (full_) t_.ringT.alloc(NR * td.m);
+        if (mixed_) { mx_f_.alloc(NR); mx_ya_.alloc(NR); mx_yb_.alloc(NR); }
         const size_t Rp = td.Rp;
         t_.c_rho.alloc(Rp); t_.c_alpha.alloc(Rp); t_.c_alpha_prev.alloc(Rp); t_.c_beta_prev.alloc(Rp);
         t_.c_swc.alloc(Rp); t_.c_swcm.alloc(Rp);
@@ -1521,9 +1538,10 @@ template <typename T> class TileSolver {
         k_ctrl<<<td.Rp, kBlock, 0, st_>>>(td.K, td.Rp, td.Gs, n, 0, t_.part_c.get(), cs, ss);
         proj_update(cs, ss, 0, rp);
         k_update_r<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_alpha.get(), t_.q.get(),
-                                         t_.r.get(), t_.res.get(), t_.d.get(), t_.part_d.get(), cheb_ok_ ? 0 : 1);
+                                         t_.r.get(), t_.res.get(), t_.d.get(), t_.part_d.get(), cheb_ok_ ? 0 : 1,
+                                         r32_out());
         k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 0, inner_tol_, cs);
-        const bool fused = inner_solve_cheb(o, cs, rp, t_.part_c.get());
+        const bool fused = inner_solve(o, cs, rp, t_.part_c.get());
         if (!fused)
             k_rho_dot<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_zres.get(), rp, t_.r.get(),
                                             t_.part_c.get());
@@ -1585,7 +1603,7 @@ template <typename T> class TileSolver {
             prof_.begin(st_, KP_UPDATE_R, 0.0);
             k_update_r<T><<<eg, eb, 0, st_>>>(td.N, td.Rp, td.Lr, t_.c_done.get(), t_.c_alpha.get(),
                                              t_.q.get(), t_.r.get(), t_.res.get(), t_.d.get(), t_.part_d.get(),
-                                             cheb_ok_ ? 0 : 1);
+                                             cheb_ok_ ? 0 : 1, r32_out());
             prof_.end(st_);
             k_col_rnorm<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.G, t_.part_d.get(), 0, inner_tol, cs);
             // rho = r'^T r comes out of the Chebyshev iteration's last step
@@ -1818,7 +1836,51 @@ template <typename T> class TileSolver {
     long long inner_total() const { return inner_total_; }
     // graph replays run no host code: the scheduler keeps the count instead
     void set_inner_total(long long v) { inner_total_ = v; }
-    int cheb_steps_per_solve() const { return cheb_steps_ - 1; }
+    int cheb_steps_per_solve() const { return mixed_ ? mx_steps_per_solve() : cheb_steps_ - 1; }
+
+    // Algorithmic bytes of one outer iteration of one column in projected
+    // carry with the current inner plan (vectors of N elements read or
+    // written once: seed product p, q; r update r, q, r; p update r', p, p;
+    // the Chebyshev steps' gathered, streamed and written vectors; plus the
+    // matrices once per product launch, shared by the tile's Rp columns).
+    // The projections' scalar updates and the column reductions are left
+    // out (K M scalars against N-long vectors).
+    double col_iter_inner_bytes() const {
+        const auto &td = t_.td;
+        const double s = sizeof(cpx<T>), N = td.N;
+        const double mat = static_cast<double>(pr_.nnzb) * pr_.B * pr_.B;
+        double v = 0.0, m = 0.0;
+        if (!cheb_ok_) return 0.0;
+        if (mixed_) {
+            const int nr = static_cast<int>(mx_plan_.size());
+            for (int j = 0; j < nr; ++j) {
+                const int K = mx_plan_[j];
+                for (int kk = 1; kk < K; ++kk) {
+                    const int mode = kk == 1 ? 0 : kk == 2 ? 1 : 2;
+                    const bool last = kk == K - 1;
+                    const int fin = last ? (j == 0 ? 1 : 2) : 0;
+                    v += 8.0 + (mode >= 1 ? 8.0 : 0.0) + (mode == 2 ? 8.0 : 0.0);
+                    v += fin == 0 ? 8.0 : fin == 1 ? 16.0 : 32.0;
+                    if (last && j == nr - 1) v += 16.0;   // r for the dot
+                    m += 4.0 * mat;
+                }
+                if (j > 0) { v += 40.0; m += 8.0 * mat; }
+            }
+        } else {
+            for (int k = 1; k < cheb_steps_; ++k) {
+                v += s * (k == 1 ? 2 : k == 2 ? 3 : 4);
+                m += sizeof(T) * mat;
+            }
+        }
+        return v * N + m / td.Rp;
+    }
+    double col_iter_bytes() const {
+        const auto &td = t_.td;
+        const double s = sizeof(cpx<T>), N = td.N;
+        const double mat = static_cast<double>(pr_.nnzb) * pr_.B * pr_.B;
+        const double outer = (2.0 + 3.0 + 3.0) * s * N + (mixed_ ? 8.0 * N : 0.0) + 2.0 * sizeof(T) * mat / td.Rp;
+        return outer + col_iter_inner_bytes();
+    }
     int switches() const { return switches_; }
     long long shift_rhs_iters() const { return shift_rhs_iters_; }
     double worst_res() const { return worst_res_; }
@@ -1887,6 +1949,7 @@ template <typename T> class TileSolver {
     // S y = r; with dot_part, returns true when the partials of y^T r over
     // the product kernels' row groups (td.Gs) were left there as well
     bool inner_solve(const gsc_opts &o, ColState cs, cpx<T> *y, c128 *dot_part = nullptr) {
+        if (cheb_ok_ && mixed_) return inner_solve_mx(cs, reinterpret_cast<c128 *>(y), dot_part);
         if (cheb_ok_) return inner_solve_cheb(o, cs, y, dot_part);
         inner_solve_cg(o, cs, y);
         return false;
@@ -1916,6 +1979,7 @@ template <typename T> class TileSolver {
         cheb_rho_ = (std::sqrt(kappa) - 1.0) / (std::sqrt(kappa) + 1.0);
         cheb_max_ = o.inner_max_iter;
         cheb_steps_ = cheb_steps_for(tol_in);
+        if (mixed_) mx_plan_ = mx_plan_for(tol_in);
         cheb_ok_ = true;
         cheb_lo_ = h[0];
         cheb_hi_ = h[1];
@@ -1941,11 +2005,132 @@ template <typename T> class TileSolver {
         if (!cheb_ok_ || !(inner_tol_base_ > 0.0)) return false;
         double t = worst > 0.0 ? inner_tol_base_ / worst : inner_tol_base_;
         t = std::max(std::min(t, kRelaxCap), inner_tol_base_);
-        const int k = cheb_steps_for(t);
-        const bool changed = k != cheb_steps_;
+        bool changed;
+        if (mixed_) {
+            std::vector<int> plan = mx_plan_for(t);
+            changed = plan != mx_plan_;
+            mx_plan_ = std::move(plan);
+        } else {
+            const int k = cheb_steps_for(t);
+            changed = k != cheb_steps_;
+            cheb_steps_ = k;
+        }
         if (changed || !steps_only) inner_tol_ = t;
-        cheb_steps_ = k;
         return changed;
+    }
+
+    // Rounds of the mixed inner solve for a relative tolerance tau: each
+    // complex64 round reduces its right-hand side to at most kMxFloor (well
+    // above what FP32 arithmetic resolves), the FP64 residual between rounds
+    // carries the rest; entries are the step counts K_j of the rounds.
+    std::vector<int> mx_plan_for(double tau) const {
+        std::vector<int> plan;
+        double rem = tau;
+        while (true) {
+            plan.push_back(cheb_steps_for(std::max(rem, kMxFloor)));
+            if (rem >= kMxFloor * (1.0 - 1e-9) || plan.size() == 4) break;
+            rem /= kMxFloor;
+        }
+        return plan;
+    }
+
+    // Mixed inner solve of S Y = r (Y complex128, the ring slot): rounds of
+    // the complex64 Chebyshev iteration (FP32 S and arithmetic, iterates in
+    // complex64) refined in FP64: round 1 solves S y = r, round j > 1 solves
+    // S y = r - S Y for the FP64 residual of the sum so far, and every round
+    // adds its last iterate to Y in FP64 (iterative refinement).  The last
+    // step of the last round also forms the partials of Y^T r (the next rho)
+    // when dot_part is given.  Then the residual check of the Chebyshev
+    // path: columns whose last round ended above tol / rho take one more
+    // refinement round, and a final check flags those still above tol.  No
+    // host synchronisation (graph-capturable); the plan comes from the
+    // current inner tolerance.
+    bool inner_solve_mx(ColState cs, c128 *Y, c128 *dot_part) {
+        if constexpr (!std::is_same<T, double>::value) {
+            (void)cs; (void)Y; (void)dot_part;
+            throw Error(GSC_E_ARG, "the mixed inner solve runs on the FP64 seed process");
+        } else {
+        auto &td = t_.td;
+        const size_t NR = static_cast<size_t>(td.N) * td.Rp;
+        if (!r32_fresh_) {
+            k_to_c64<<<div_up(static_cast<int64_t>(NR), 256), 256, 0, st_>>>(NR, t_.r.get(), mx_f_.get());
+            GSC_HIP(hipGetLastError());
+        }
+        r32_fresh_ = false;
+        const bool dot = dot_part != nullptr;
+        const float *S32 = pr_.S32.get();
+        const double *S64 = pr_.S.get();
+        const double sigma = cheb_theta_ / cheb_delta_;
+        c64 *buf[2] = {mx_ya_.get(), mx_yb_.get()};
+        const int cb = td.cb > 0 ? td.cb : td.Rp;
+        const double vec = static_cast<double>(last_active_) * td.N;
+        // one complex64 round of K - 1 steps on S y = f (f in mx_f_)
+        auto round = [&](int K, int fin, bool with_dot, const int *skip, int c0, int w, int dot_active_only,
+                         double cols, bool timed) {
+            double rho_prev = 1.0 / sigma, bytes = 0.0;
+            if (timed) prof_.begin_group(st_, KP_CHEB_MX);
+            for (int kk = 1; kk < K; ++kk) {
+                const double rho = 1.0 / (2.0 * sigma - rho_prev);
+                const double c1 = rho * rho_prev, c2 = 2.0 * rho / cheb_delta_;
+                const int mode = kk == 1 ? 0 : kk == 2 ? 1 : 2;
+                const bool last = kk == K - 1;
+                const int f = last ? fin : 0;
+                launch_cheb_mx(st_, pr_, td, mode, f, last && with_dot, c0, w, S32, buf[kk % 2], mx_f_.get(),
+                               buf[(kk + 1) % 2], Y, t_.r.get(), skip, 1.0 / cheb_theta_, c1, c2, t_.part_d.get(),
+                               dot_part, dot_active_only);
+                // algorithmic bytes per column element: gathered y (or f),
+                // f and y_{k-1} streamed, y_{k+1} written; a final step writes
+                // Y (complex128, after reading it for fin 2) and reads r for
+                // the dot
+                double b = 8.0 + (mode >= 1 ? 8.0 : 0.0) + (mode == 2 ? 8.0 : 0.0);
+                b += f == 0 ? 8.0 : f == 1 ? 16.0 : 32.0;
+                if (last && with_dot) b += 16.0;
+                bytes += b * cols * td.N;
+                rho_prev = rho;
+            }
+            if (timed) prof_.end_group(st_, K - 1, bytes);
+        };
+        const int nr = static_cast<int>(mx_plan_.size());
+        const double wfrac = 1.0 / td.Rp;
+        for (int c0 = 0; c0 < td.Rp; c0 += cb) {
+            const int w = std::min(cb, td.Rp - c0);
+            const double cols = vec / td.N * w * wfrac;
+            for (int j = 0; j < nr; ++j) {
+                if (j > 0) {
+                    prof_.begin(st_, KP_MX_RESID, 40.0 * cols * td.N);
+                    launch_mx_resid(st_, pr_, td, c0, w, S64, Y, t_.r.get(), mx_f_.get(), t_.c_done.get(),
+                                    t_.part_d.get());
+                    prof_.end(st_);
+                }
+                round(mx_plan_[j], j == 0 ? 1 : 2, dot && j == nr - 1, t_.c_done.get(), c0, w, 0, cols, true);
+            }
+        }
+        k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_ / cheb_rho_, 0, cs);
+        // one more refinement round for the columns that failed the check
+        // (the launches skip every other column; neither timed nor counted)
+        for (int c0 = 0; c0 < td.Rp; c0 += cb) {
+            const int w = std::min(cb, td.Rp - c0);
+            launch_mx_resid(st_, pr_, td, c0, w, S64, Y, t_.r.get(), mx_f_.get(), t_.c_inner_done.get(),
+                            t_.part_d.get());
+            round(kMxSafetySteps, 2, dot, t_.c_inner_done.get(), c0, w, 1, 0.0, false);
+        }
+        k_cheb_check<<<td.Rp, kBlock, 0, st_>>>(td.Rp, td.Gs, t_.part_d.get(), inner_tol_, 1, cs);
+        GSC_HIP(hipGetLastError());
+        inner_total_ += mx_steps_per_solve();
+        return dot;
+        }
+    }
+    // products with S per mixed inner solve (Chebyshev steps and FP64
+    // residual passes), without the safety round
+    int mx_steps_per_solve() const {
+        int n = 0;
+        for (size_t j = 0; j < mx_plan_.size(); ++j) n += mx_plan_[j] - 1 + (j > 0 ? 1 : 0);
+        return n;
+    }
+    c64 *r32_out() {
+        if (!mixed_ || !cheb_ok_) return nullptr;
+        r32_fresh_ = true;
+        return mx_f_.get();
     }
 
     // Chebyshev iteration for S y = r (r in t_.r), y_K written to `ytarget`,
@@ -2099,7 +2284,16 @@ template <typename T> class TileSolver {
     double cheb_theta_ = 1.0, cheb_delta_ = 0.5, cheb_rho_ = 0.5, cheb_lo_ = 0.0, cheb_hi_ = 0.0;
     int cheb_steps_ = 0, cheb_max_ = 200;
     double inner_tol_base_ = 0.0;     // the fixed inner tolerance of the solve
-    static constexpr double kRelaxCap = 1e-6;
+    static constexpr double kRelaxCap = 1e-4;
+    // mixed inner solve: precision flag, complex64 right-hand side (r after
+    // each residual update, or the FP64 residual between rounds) and the two
+    // alternating complex64 iterates; the plan of rounds
+    bool mixed_ = false;
+    bool r32_fresh_ = false;
+    DevBuf<c64> mx_f_, mx_ya_, mx_yb_;
+    std::vector<int> mx_plan_;
+    static constexpr double kMxFloor = 1e-5;
+    static constexpr int kMxSafetySteps = 4;
     long long cheb_extra_ = 0;
     long long inner_total_ = 0;
     int switches_ = 0;
@@ -2271,6 +2465,8 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
         DevBuf<Status> dstat;
         Status *hstat = nullptr;
         int n = 0;
+        long long col_iters = 0;            // column-iterations accounted so far
+        double bytes = 0.0, bytes_inner = 0.0;
         bool inflight = false, finished = false, graphed = false;
         gsc_opts o{};
     };
@@ -2348,6 +2544,12 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
                 progress = true;
                 const Status s = *L.hstat;
                 L.ts->note_status(s);
+                // algorithmic bytes of the iterations since the last poll,
+                // with the inner plan they ran with
+                const double dci = static_cast<double>(s.col_iters - L.col_iters);
+                L.col_iters = s.col_iters;
+                L.bytes += dci * L.ts->col_iter_bytes();
+                L.bytes_inner += dci * L.ts->col_iter_inner_bytes();
                 if (s.active_cols == 0 || L.n >= L.o.max_iter) {
                     L.finished = true;
                     --remaining;
@@ -2375,6 +2577,8 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
                 rq.stats->outer_iters = iters_out[jobs[j].sys];
                 rq.stats->inner_iters += L.ts->inner_total();
                 rq.stats->shift_rhs_iters += L.ts->shift_rhs_iters();
+                rq.stats->alg_bytes += L.bytes;
+                rq.stats->alg_bytes_inner += L.bytes_inner;
             }
             if (L.ts->worst_res() > L.o.tol || (L.ts->flags() & FLAG_INNER)) result = GSC_NOT_CONVERGED;
         }
@@ -2504,30 +2708,29 @@ gsc_status lanczos_typed(Ctx &ctx, LanczosRequest &req) {
 
 }  // namespace
 
+// GSC_C64 runs the whole seed process in complex64 (TileSolver<float>);
+// GSC_MIXED keeps it in FP64 and runs the inner S-solve in complex64 rounds
+// refined in FP64 (TileSolver<double>); both read the FP32 copy of S.
 gsc_status run_batched(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_iters, int max_streams,
                        std::vector<int> &iters) {
-    bool mixed = false;
-    for (auto &r : reqs) mixed |= r.opts.precision == GSC_MIXED;
-    if (mixed) {
-        for (auto &r : reqs) ensure_f32(const_cast<Pair &>(*r.pair));
-        return batched_typed<float>(ctx, reqs, graph_iters, max_streams, iters);
+    bool c64 = false;
+    for (auto &r : reqs) {
+        c64 |= r.opts.precision == GSC_C64;
+        if (r.opts.precision != GSC_FP64) ensure_f32(const_cast<Pair &>(*r.pair));
     }
+    if (c64) return batched_typed<float>(ctx, reqs, graph_iters, max_streams, iters);
     return batched_typed<double>(ctx, reqs, graph_iters, max_streams, iters);
 }
 
 gsc_status run_solve(Ctx &ctx, SolveRequest &req) {
-    if (req.opts.precision == GSC_MIXED) {
-        ensure_f32(const_cast<Pair &>(*req.pair));
-        return solve_typed<float>(ctx, req);
-    }
+    if (req.opts.precision != GSC_FP64) ensure_f32(const_cast<Pair &>(*req.pair));
+    if (req.opts.precision == GSC_C64) return solve_typed<float>(ctx, req);
     return solve_typed<double>(ctx, req);
 }
 
 gsc_status run_lanczos(Ctx &ctx, LanczosRequest &req) {
-    if (req.opts.precision == GSC_MIXED) {
-        ensure_f32(const_cast<Pair &>(*req.pair));
-        return lanczos_typed<float>(ctx, req);
-    }
+    if (req.opts.precision != GSC_FP64) ensure_f32(const_cast<Pair &>(*req.pair));
+    if (req.opts.precision == GSC_C64) return lanczos_typed<float>(ctx, req);
     return lanczos_typed<double>(ctx, req);
 }
 

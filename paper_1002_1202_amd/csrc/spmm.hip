@@ -290,6 +290,210 @@ template void launch_cheb_step<float>(hipStream_t, const Pair &, const TileDims 
                                       const c64 *, const c64 *, c64 *, const int *, double, double, double,
                                       double *, c128 *, int);
 
+// ------------------------------------------------------------------ mixed inner solve
+// Complex64 rounds of the inner solve S Y = r refined in FP64 (iterative
+// refinement).  Inside a round the iterates y live in complex64 and each step
+// runs in FP32 arithmetic against the FP32 copy of S, solving S y = f for the
+// round's right-hand side f (complex64).  The round's last step (FIN) does not
+// store its iterate: it adds it to the FP64 solution Y (FIN 1: Y = y, FIN 2:
+// Y += y), and with DOT it also forms the partial of Y^T r (unconjugated,
+// FP64: the next rho of the outer iteration, eq. CGp:p) from the FP64 r.
+// Between rounds k_mx_resid forms the next right-hand side f = r - S Y in
+// FP64, so rounding in the complex64 rounds limits only how fast the
+// refinement converges, not where it ends.
+template <int B, int MODE, int FIN, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_cheb_mx(
+    int nb, int Rp, int col0, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    const float *__restrict__ Sv, const c64 *__restrict__ y, const c64 *__restrict__ f, c64 *__restrict__ yio,
+    c128 *__restrict__ Y, const c128 *__restrict__ r, const int *__restrict__ skip, float inv_theta, float c1,
+    float c2, double *__restrict__ partial, c128 *__restrict__ dpart, int dot_active_only) {
+    int cx, g;
+    xcd_remap_chunks(cx, g);
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_id();
+    const int col = col0 + cx * 64 + lane;
+    const bool act = !skip[col];
+    double acc2 = 0.0;
+    c128 dacc{0.0, 0.0};
+    const int row_step = kWavesPerBlock * static_cast<int>(gridDim.y);
+    const c64 *x = MODE == 0 ? f : y;
+    if (__ballot(act) != 0) {
+        for (int I = kWavesPerBlock * g + wv; I < nb; I += row_step) {
+            c64 aS[B], own[B];
+#pragma unroll
+            for (int a = 0; a < B; ++a) { aS[a] = {0, 0}; own[a] = {0, 0}; }
+            const int b0 = rowptr[I], b1 = rowptr[I + 1];
+            c64 xv[B];
+#pragma unroll
+            for (int c = 0; c < B; ++c) xv[c] = {0, 0};
+#pragma unroll 2
+            for (int b = b0; b < b1; ++b) {
+                const int J = colidx[b];
+                const float *sb = Sv + static_cast<size_t>(b) * B * B;
+                if (act) {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) xv[c] = x[static_cast<size_t>(J * B + c) * Rp + col];
+                }
+                if (J == I) {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) own[c] = xv[c];
+                }
+#pragma unroll
+                for (int a = 0; a < B; ++a) {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) {
+                        const float sv = sb[a * B + c];
+                        aS[a].re = fmaf(sv, xv[c].re, aS[a].re);
+                        aS[a].im = fmaf(sv, xv[c].im, aS[a].im);
+                    }
+                }
+            }
+            if (!act) continue;
+#pragma unroll
+            for (int a = 0; a < B; ++a) {
+                const size_t e = static_cast<size_t>(I * B + a) * Rp + col;
+                double res2;
+                c64 rv;
+                const c64 ynew = cheb_next<float, MODE, false>(own[a], aS[a], f, yio, e, inv_theta, c1, c2, res2, rv);
+                acc2 += res2;
+                if constexpr (FIN == 0) {
+                    yio[e] = ynew;
+                } else {
+                    c128 v = ccast<double>(ynew);
+                    if constexpr (FIN == 2) v = Y[e] + v;
+                    Y[e] = v;
+                    if constexpr (DOT) dacc = dacc + v * r[e];
+                }
+            }
+        }
+    }
+    __shared__ double red[kWavesPerBlock][64];
+    red[wv][lane] = acc2;
+    if constexpr (DOT) {
+        __shared__ c128 redc[kWavesPerBlock][64];
+        redc[wv][lane] = dacc;
+        __syncthreads();
+        if (threadIdx.x < 64 && (act || !dot_active_only)) {
+            c128 t = redc[0][lane];
+#pragma unroll
+            for (int k = 1; k < kWavesPerBlock; ++k) t = t + redc[k][lane];
+            dpart[static_cast<size_t>(g) * Rp + col] = t;
+        }
+    } else {
+        __syncthreads();
+    }
+    if (threadIdx.x < 64) {
+        double t = red[0][lane];
+#pragma unroll
+        for (int k = 1; k < kWavesPerBlock; ++k) t += red[k][lane];
+        partial[static_cast<size_t>(g) * Rp + col] = t;
+    }
+}
+
+// f = r - S Y in FP64 (S, Y, r in FP64), stored in complex64 as the
+// right-hand side of the next complex64 round; partial ||f||^2.
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_mx_resid(
+    int nb, int Rp, int col0, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    const double *__restrict__ Sv, const c128 *__restrict__ Y, const c128 *__restrict__ r, c64 *__restrict__ f,
+    const int *__restrict__ skip, double *__restrict__ partial) {
+    int cx, g;
+    xcd_remap_chunks(cx, g);
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_id();
+    const int col = col0 + cx * 64 + lane;
+    const bool act = !skip[col];
+    double acc2 = 0.0;
+    const int row_step = kWavesPerBlock * static_cast<int>(gridDim.y);
+    if (__ballot(act) != 0) {
+        for (int I = kWavesPerBlock * g + wv; I < nb; I += row_step) {
+            c128 aS[B];
+#pragma unroll
+            for (int a = 0; a < B; ++a) aS[a] = {0, 0};
+            const int b0 = rowptr[I], b1 = rowptr[I + 1];
+            c128 xv[B];
+#pragma unroll
+            for (int c = 0; c < B; ++c) xv[c] = {0, 0};
+#pragma unroll 2
+            for (int b = b0; b < b1; ++b) {
+                const int J = colidx[b];
+                const double *sb = Sv + static_cast<size_t>(b) * B * B;
+                if (act) {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) xv[c] = Y[static_cast<size_t>(J * B + c) * Rp + col];
+                }
+#pragma unroll
+                for (int a = 0; a < B; ++a) {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) {
+                        const double sv = sb[a * B + c];
+                        aS[a].re = fma(sv, xv[c].re, aS[a].re);
+                        aS[a].im = fma(sv, xv[c].im, aS[a].im);
+                    }
+                }
+            }
+            if (!act) continue;
+#pragma unroll
+            for (int a = 0; a < B; ++a) {
+                const size_t e = static_cast<size_t>(I * B + a) * Rp + col;
+                const c128 d = r[e] - aS[a];
+                f[e] = ccast<float>(d);
+                acc2 += d.re * d.re + d.im * d.im;
+            }
+        }
+    }
+    __shared__ double red[kWavesPerBlock][64];
+    red[wv][lane] = acc2;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double t = red[0][lane];
+#pragma unroll
+        for (int k = 1; k < kWavesPerBlock; ++k) t += red[k][lane];
+        partial[static_cast<size_t>(g) * Rp + col] = t;
+    }
+}
+
+void launch_cheb_mx(hipStream_t st, const Pair &pr, const TileDims &td, int mode, int fin, bool dot, int col0,
+                    int ncols, const float *Sv, const c64 *y, const c64 *f, c64 *yio, c128 *Y, const c128 *r,
+                    const int *skip, double inv_theta, double c1, double c2, double *partial, c128 *dpart,
+                    int dot_active_only) {
+    GSC_REQUIRE(col0 % 64 == 0 && ncols % 64 == 0 && ncols > 0 && col0 + ncols <= td.Rp,
+                "Chebyshev column block outside the tile");
+    GSC_REQUIRE(mode >= 0 && mode <= 2 && fin >= 0 && fin <= 2, "bad mixed Chebyshev step");
+    GSC_REQUIRE(!dot || (fin > 0 && dpart != nullptr && r != nullptr), "the fused dot needs a final step");
+    GSC_REQUIRE(fin == 0 || Y != nullptr, "a final step needs the FP64 solution");
+    dim3 grid(ncols / 64, td.Gs), block(kBlock);
+    const float it = static_cast<float>(inv_theta), a = static_cast<float>(c1), b = static_cast<float>(c2);
+#define GSC_MX(BB, M, F, D)                                                                                      \
+    k_cheb_mx<BB, M, F, D><<<grid, block, 0, st>>>(td.nb, td.Rp, col0, pr.rowptr.get(), pr.colidx.get(), Sv, y, \
+                                                   f, yio, Y, r, skip, it, a, b, partial, dpart, dot_active_only)
+#define GSC_MX_F(BB, M)                                                              \
+    if (fin == 0) { GSC_MX(BB, M, 0, false); }                                       \
+    else if (fin == 1) { if (dot) GSC_MX(BB, M, 1, true); else GSC_MX(BB, M, 1, false); } \
+    else { if (dot) GSC_MX(BB, M, 2, true); else GSC_MX(BB, M, 2, false); }
+#define GSC_MX_B(BB) \
+    if (mode == 0) { GSC_MX_F(BB, 0) } else if (mode == 1) { GSC_MX_F(BB, 1) } else { GSC_MX_F(BB, 2) }
+    if (pr.B == 4) { GSC_MX_B(4) } else { GSC_MX_B(6) }
+#undef GSC_MX_B
+#undef GSC_MX_F
+#undef GSC_MX
+    GSC_HIP(hipGetLastError());
+}
+
+void launch_mx_resid(hipStream_t st, const Pair &pr, const TileDims &td, int col0, int ncols, const double *Sv,
+                     const c128 *Y, const c128 *r, c64 *f, const int *skip, double *partial) {
+    GSC_REQUIRE(col0 % 64 == 0 && ncols % 64 == 0 && ncols > 0 && col0 + ncols <= td.Rp,
+                "Chebyshev column block outside the tile");
+    dim3 grid(ncols / 64, td.Gs), block(kBlock);
+    if (pr.B == 4)
+        k_mx_resid<4><<<grid, block, 0, st>>>(td.nb, td.Rp, col0, pr.rowptr.get(), pr.colidx.get(), Sv, Y, r, f,
+                                              skip, partial);
+    else
+        k_mx_resid<6><<<grid, block, 0, st>>>(td.nb, td.Rp, col0, pr.rowptr.get(), pr.colidx.get(), Sv, Y, r, f,
+                                              skip, partial);
+    GSC_HIP(hipGetLastError());
+}
+
 // ------------------------------------------------------------------ launchers
 // Row-group geometry of the product kernels (td.Gs row groups; every
 // reduction of their partials uses td.Gs).  One block row per wave where the

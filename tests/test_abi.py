@@ -93,4 +93,5 @@ def test_option_defaults_and_binding():
                       precision="mixed", carry="projected")
     assert (m.tol, m.fuse_steps, m.cheb_block, m.inner_relax, m.graph_iters) == (1e-6, 12, 128, 1, 8)
     assert (m.precision, m.carry) == (_lib.MIXED, _lib.CARRY_PROJECTED)
+    assert api.make_opts(precision="c64").precision == _lib.C64
     assert list(m.reserved) == [0, 0]

@@ -40,7 +40,8 @@ def diagonal_pair(ctx, nat, B, seed):
     return pair, eps
 
 
-@pytest.mark.parametrize("B,inner,prec", [(4, 2, "fp64"), (4, 1, "fp64"), (6, 2, "fp64"), (4, 2, "mixed")])
+@pytest.mark.parametrize("B,inner,prec", [(4, 2, "fp64"), (4, 1, "fp64"), (6, 2, "fp64"), (4, 2, "mixed"),
+                                          (6, 2, "mixed"), (4, 2, "c64")])
 def test_identity_overlap_diagonal_closed_form(ctx, B, inner, prec):
     from paper_1002_1202_amd import api
     print(f"case: S = I, diagonal H, B={B} inner={inner} {prec}", flush=True)
@@ -50,28 +51,26 @@ def test_identity_overlap_diagonal_closed_form(ctx, B, inner, prec):
     z = shift_grid(-20.0, 0.0, 9, 0.1)
     rhs = np.arange(n)
     g = 1.0 / (z[:, None] - eps[None, :])                     # [K][n]
-    tol_g = 1e-12 if prec == "fp64" else 1e-5
-    res = api.solve(ctx, pair, z, rhs=rhs, tol=1e-13 if prec == "fp64" else 1e-6, inner_method=inner,
-                    precision=prec)
+    tol_g = {"fp64": 1e-12, "mixed": 1e-11, "c64": 1e-5}[prec]
+    tol = 1e-6 if prec == "c64" else 1e-13
+    res = api.solve(ctx, pair, z, rhs=rhs, tol=tol, inner_method=inner, precision=prec)
     assert res.status == 0 and res.converged.all()
     ref = np.zeros((len(z), n, n), dtype=complex)
     ref[:, np.arange(n), np.arange(n)] = g
     print(f"  iters={res.outer_iters} err={rel(res.G_cols, ref):.2e}", flush=True)
     assert res.outer_iters <= 2
     assert rel(res.G_cols, ref) < tol_g
-    resp = api.solve(ctx, pair, z, rhs=rhs, tol=1e-13 if prec == "fp64" else 1e-6, inner_method=inner,
-                     precision=prec, carry="projected", proj=rhs[:, None])
+    resp = api.solve(ctx, pair, z, rhs=rhs, tol=tol, inner_method=inner, precision=prec, carry="projected",
+                     proj=rhs[:, None])
     assert rel(resp.G_proj[:, :, 0], g) < tol_g
     w = trapezoid_weights(z)
-    q, e, eb, _ = api.mulliken_band(ctx, pair, z, w, rhs, tol=1e-13 if prec == "fp64" else 1e-6,
-                                    inner_method=inner, precision=prec)
+    q, e, eb, _ = api.mulliken_band(ctx, pair, z, w, rhs, tol=tol, inner_method=inner, precision=prec)
     q0 = -(2.0 / np.pi) * (w[:, None] * g.imag).sum(0)
     e0 = -(2.0 / np.pi) * ((w * z.real)[:, None] * g.imag).sum(0)
     assert np.abs(q - q0).max() < tol_g * np.abs(q0).max()
     assert np.abs(e - e0).max() < tol_g * np.abs(e0).max()
     assert abs(eb - e0.sum()) < tol_g * np.abs(e0).sum()
-    lz = api.lanczos_green(ctx, pair, z, rhs, m_max=8, tol=1e-13 if prec == "fp64" else 1e-6,
-                           check_every=1, precision=prec)
+    lz = api.lanczos_green(ctx, pair, z, rhs, m_max=8, tol=tol, check_every=1, precision=prec)
     print(f"  lanczos steps {lz.steps.min()}..{lz.steps.max()} err={rel(lz.G_diag, g):.2e}", flush=True)
     assert lz.steps.max() <= (1 if prec == "fp64" else 4)
     assert rel(lz.G_diag, g) < tol_g
