@@ -104,16 +104,19 @@ typedef struct {
                               interval is positive, else 1                     */
     int graph_iters;       /* [0 = 4] gsc_solve_batched: outer iterations per
                               captured hipGraph launch (between status polls)  */
-    int stream_hint;       /* [0 = auto = 1] 1: the Chebyshev step's streamed
+    int stream_hint;       /* [0 = auto] 1: the Chebyshev step's streamed
                               vectors are loaded and stored with the default
                               cache policy, 2: nontemporal (kept out of L2 so
-                              the gathered halo stays resident)               */
+                              the gathered halo stays resident); auto = 2 for
+                              tiles whose automatic column block is one chunk
+                              (see cheb_block), else 1                        */
     int cheb_block;        /* [0 = auto] columns per Chebyshev launch block (a
                               multiple of 64, row layout): every step of the
                               inner solve runs on one block of columns at a
                               time; auto sizes the block so that the step's
                               three vectors fit the 256 MB infinity cache
-                              (no blocking when the tile already fits)        */
+                              (no blocking when the tile already fits; one
+                              64-column chunk when not even two chunks fit)   */
     int inner_relax;       /* [0] 1: relaxed inner tolerance (Chebyshev inner
                               solves; gsc_solve_batched captures a job's graph
                               anew when its step count changes): each outer
@@ -124,7 +127,10 @@ typedef struct {
                               unconverged shift stays at inner_tol relative
                               to ||b||.  0 keeps the fixed inner_tol of the
                               method.                                         */
-    int reserved[2];
+    int batch_streams;     /* [0 = auto = 8] gsc_solve_batched: jobs (system,
+                              rhs tile) iterating concurrently, each on its
+                              own stream                                      */
+    int reserved[1];
 } gsc_opts;
 
 /* Statistics.  The three arrays are caller-owned HOST arrays of

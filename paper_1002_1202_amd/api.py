@@ -198,7 +198,7 @@ def spmm(ctx: Context, pair: Pair, X, alpha_S):
 def make_opts(tol=1e-10, max_iter=5000, inner_tol=0.0, inner_max_iter=200, precision="fp64",
               carry="full", seed_index=-1, fuse_steps=0, rhs_tile=0, recheck=False,
               spmm_kernel=0, inner_method=0, graph_iters=0, stream_hint=0, cheb_block=0,
-              inner_relax=False) -> L.Opts:
+              inner_relax=False, batch_streams=0) -> L.Opts:
     """gsc_opts with the library's defaults for every option not given (the
     fields and their meaning are those of gsc_opts in include/gsc.h).
     ``precision``: "fp64"; "mixed" (FP64 seed process, inner S-solve in
@@ -220,6 +220,7 @@ def make_opts(tol=1e-10, max_iter=5000, inner_tol=0.0, inner_max_iter=200, preci
     o.stream_hint = stream_hint
     o.cheb_block = cheb_block
     o.inner_relax = int(inner_relax)
+    o.batch_streams = batch_streams
     return o
 
 

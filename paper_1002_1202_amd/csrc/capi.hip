@@ -928,6 +928,7 @@ gsc_status gsc_solve_batched(gsc_ctx *ctx, int nsys, const gsc_problem *problems
         if (opts) o = *opts;
         validate_opts(o);
         GSC_REQUIRE(o.graph_iters >= 0, "graph_iters must be >= 0");
+        GSC_REQUIRE(o.batch_streams >= 0 && o.batch_streams <= 64, "batch_streams must be 0 .. 64");
         o.carry = GSC_CARRY_PROJECTED;
         const int graph_iters = o.graph_iters > 0 ? o.graph_iters : 4;
         DeviceGuard g(ctx->c.device);
@@ -974,7 +975,8 @@ gsc_status gsc_solve_batched(gsc_ctx *ctx, int nsys, const gsc_problem *problems
         GSC_HIP(hipDeviceSynchronize());
         GSC_HIP(hipEventRecord(e0, st));
         std::vector<int> iters;
-        const gsc_status s = run_batched(ctx->c, reqs, graph_iters, 8, iters);
+        const gsc_status s = run_batched(ctx->c, reqs, graph_iters, o.batch_streams > 0 ? o.batch_streams : 8,
+                                         iters);
         GSC_HIP(hipDeviceSynchronize());
         GSC_HIP(hipEventRecord(e1, st));
         GSC_HIP(hipEventSynchronize(e1));
