@@ -246,6 +246,23 @@ gsc_status gsc_ased_vjp(gsc_ctx *ctx, const gsc_ased_geom *geom, double scale,
 gsc_status gsc_spmm(gsc_ctx *ctx, const gsc_pair *pair, int nrhs, const double *alpha_S,
                     const double *X, double *Y, int mem);
 
+/* Allocation-free variant of gsc_spmm, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The same product and layout; X and Y are DEVICE
+ * memory of the context's device, alpha_S HOST [nrhs] complex.  Its
+ * temporaries (per-column shifts, the partial dots of the product kernel,
+ * and padded copies of X and Y when nrhs is not a multiple of 64) live in
+ * one fixed scratch array of 64 MiB per device, part of the library's code
+ * object and held until the process ends; the call performs no device or
+ * pinned-host allocation.  GSC_E_ARG, before any device work, when the call
+ * needs more than the 64 MiB (with padding about 32 N ceil64(nrhs) bytes).
+ * Every call on one device shares that device's scratch, which keeps the
+ * last call's contents: calls that overlap on one device (other host
+ * threads or other contexts) race and must be serialised by the caller.
+ * Synchronises the context's stream before returning. */
+gsc_status gsc_spmm_noalloc(gsc_ctx *ctx, const gsc_pair *pair, int nrhs, const double *alpha_S,
+                            const double *X, double *Y);
+
 /* ---- the shifted solve (Sec. 3.3) ---------------------------------------- */
 /* 1 <= nshift <= 65535 (every entry point that takes shifts).
  * rhs: unit vectors e_{rhs_idx[r]} (rhs_idx HOST [nrhs]) or, if rhs_idx is

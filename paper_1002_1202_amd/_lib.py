@@ -72,6 +72,7 @@ SIGNATURES = {
     "gsc_ased_build": (C.c_int, [_VP, C.POINTER(AsedGeom), C.c_double, _VP, _DP]),
     "gsc_ased_vjp": (C.c_int, [_VP, C.POINTER(AsedGeom), C.c_double, _VP, _VP, _VP, C.c_int, _DP]),
     "gsc_spmm": (C.c_int, [_VP, _VP, C.c_int, _DP, _VP, _VP, C.c_int]),
+    "gsc_spmm_noalloc": (C.c_int, [_VP, _VP, C.c_int, _DP, _VP, _VP]),
     "gsc_solve": (C.c_int, [_VP, _VP, C.c_int, _DP, C.c_int, _I64P, _VP, C.POINTER(Opts), _VP,
                             C.c_int, _I64P, _VP, C.c_int, C.POINTER(Stats)]),
     "gsc_mulliken_band": (C.c_int, [_VP, _VP, C.c_int, _DP, _DP, C.c_int, _I64P, C.POINTER(Opts),

@@ -195,6 +195,21 @@ def spmm(ctx: Context, pair: Pair, X, alpha_S):
     return Y
 
 
+def spmm_noalloc(ctx: Context, pair: Pair, X, alpha_S, Y=None):
+    """gsc_spmm_noalloc: Y = alpha_S[c] * S X[:, c] - H X[:, c] for a complex
+    (N, R) torch tensor X on the context's device; the library allocates
+    nothing (its temporaries live in a fixed per-device scratch array).  Y:
+    the caller's output tensor (allocated here when not given)."""
+    import torch
+    if not (_is_device(X) and X.dtype == torch.complex128 and X.is_contiguous()):
+        raise ValueError("X must be a contiguous complex128 device tensor")
+    alpha = _complex_view(np.broadcast_to(np.asarray(alpha_S, np.complex128), (X.shape[1],)).copy())
+    if Y is None:
+        Y = torch.empty_like(X)
+    L.check(ctx.lib.gsc_spmm_noalloc(ctx.h, pair.h, X.shape[1], _ptr(alpha), _vp(X), _vp(Y)))
+    return Y
+
+
 def make_opts(tol=1e-10, max_iter=5000, inner_tol=0.0, inner_max_iter=200, precision="fp64",
               carry="full", seed_index=-1, fuse_steps=0, rhs_tile=0, recheck=False,
               spmm_kernel=0, inner_method=0, graph_iters=0, stream_hint=0, cheb_block=0,

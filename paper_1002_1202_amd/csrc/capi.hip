@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 
 #include "csc.h"
 #include "pair.h"
@@ -110,6 +111,40 @@ __global__ void k_pad_cols(int N, int R, int Rp, const c128 *in, c128 *out, int 
     else if (c < R) out[i * R + c] = in[t];
 }
 
+// ------------------------------------------------------------------ allocation-free product
+// gsc_spmm_noalloc works in this fixed array instead of allocating: one copy
+// per device, part of the code object, held until the process ends.  In host
+// code the name is only a host-side stand-in, never a device address: host
+// code uses the address hipGetSymbolAddress returns, fetched once per device
+// (with that device current) when a context is created, and kept in the
+// context.
+constexpr size_t kScratchBytes = size_t{64} << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of `scratch` on `device`, which must be the current device.
+void *scratch_address(int device) {
+    static std::mutex mu;
+    static void *addr[64] = {};
+    GSC_REQUIRE(device >= 0 && device < 64, "device ordinal out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[device] == nullptr) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr)
+            throw Error(GSC_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        addr[device] = ptr;
+    }
+    return addr[device];
+}
+
+// per-column shift index c and zero shifts for the padding columns c >= R
+__global__ void k_noalloc_cols(int R, int Rp, c128 *z, int *seed) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= Rp) return;
+    seed[c] = c;
+    if (c >= R) z[c] = c128{0.0, 0.0};
+}
+
 void validate_opts(const gsc_opts &o) {
     GSC_REQUIRE(o.tol > 0 && std::isfinite(o.tol), "tol must be positive");
     GSC_REQUIRE(o.max_iter > 0, "max_iter must be positive");
@@ -171,6 +206,7 @@ gsc_status gsc_create(gsc_ctx **out, int device, void *stream) {
         hipDeviceProp_t prop;
         GSC_HIP(hipGetDeviceProperties(&prop, device));
         c->c.num_cu = prop.multiProcessorCount;
+        c->c.scratch = scratch_address(device);
         *out = c.release();
         return GSC_OK;
     });
@@ -317,6 +353,63 @@ gsc_status gsc_spmm(gsc_ctx *ctx, const gsc_pair *pair, int nrhs, const double *
         GSC_HIP(hipGetLastError());
         if (mem != GSC_MEM_DEVICE)
             GSC_HIP(hipMemcpyAsync(Y, yout.get(), yout.n * sizeof(c128), hipMemcpyDeviceToHost, st));
+        GSC_HIP(hipStreamSynchronize(st));
+        return GSC_OK;
+    });
+}
+
+gsc_status gsc_spmm_noalloc(gsc_ctx *ctx, const gsc_pair *pair, int nrhs, const double *alpha_S, const double *X,
+                            double *Y) {
+    return guarded([&] {
+        GSC_REQUIRE(ctx != nullptr && pair != nullptr, "ctx/pair must not be NULL");
+        GSC_REQUIRE(nrhs > 0 && alpha_S && X && Y, "bad spmm arguments");
+        GSC_REQUIRE(ctx->c.scratch != nullptr, "the context has no scratch address");
+        DeviceGuard g(ctx->c.device);
+        const Pair &p = pair->p;
+        hipStream_t st = ctx->c.stream;
+        const int N = static_cast<int>(p.n);
+        const int Rp = (nrhs + 63) / 64 * 64;
+        TileDims td{};
+        td.N = N; td.nb = static_cast<int>(p.nb); td.B = p.B; td.Rp = Rp;
+        set_spmm_geometry(td, p);
+        // the scratch: shifts [Rp], seed indices [Rp], partial dots [Gs][Rp]
+        // and, unless nrhs is a multiple of 64, padded copies of X and Y
+        const bool direct = Rp == nrhs;
+        size_t off = 0;
+        auto carve = [&off](size_t bytes) {
+            const size_t o = off;
+            off += (bytes + 255) / 256 * 256;
+            return o;
+        };
+        const size_t NRp = static_cast<size_t>(N) * Rp;
+        const size_t oz = carve(Rp * sizeof(c128));
+        const size_t os = carve(Rp * sizeof(int));
+        const size_t op = carve(static_cast<size_t>(td.Gs) * Rp * sizeof(c128));
+        const size_t ox = direct ? 0 : carve(NRp * sizeof(c128));
+        const size_t oy = direct ? 0 : carve(NRp * sizeof(c128));
+        if (off > kScratchBytes)
+            throw Error(GSC_E_ARG, "gsc_spmm_noalloc needs " + std::to_string(off) +
+                                       " bytes of scratch, more than its maximum of " +
+                                       std::to_string(kScratchBytes) + " (fewer rhs or a multiple of 64)");
+        unsigned char *base = static_cast<unsigned char *>(ctx->c.scratch);
+        c128 *dz = reinterpret_cast<c128 *>(base + oz);
+        int *dseed = reinterpret_cast<int *>(base + os);
+        c128 *part = reinterpret_cast<c128 *>(base + op);
+        GSC_HIP(hipMemcpyAsync(dz, alpha_S, static_cast<size_t>(nrhs) * sizeof(c128), hipMemcpyHostToDevice, st));
+        k_noalloc_cols<<<div_up(Rp, 256), 256, 0, st>>>(nrhs, Rp, dz, dseed);
+        const c128 *xin = reinterpret_cast<const c128 *>(X);
+        c128 *yout = reinterpret_cast<c128 *>(Y);
+        if (!direct) {
+            c128 *xp = reinterpret_cast<c128 *>(base + ox);
+            k_pad_cols<<<div_up(static_cast<int64_t>(NRp), 256), 256, 0, st>>>(N, nrhs, Rp, xin, xp, 1);
+            xin = xp;
+            yout = reinterpret_cast<c128 *>(base + oy);
+        }
+        launch_spmm_seed<double>(st, p, td, p.S.get(), p.H.get(), xin, yout, dz, dseed, nullptr, part);
+        if (!direct)
+            k_pad_cols<<<div_up(static_cast<int64_t>(NRp), 256), 256, 0, st>>>(N, nrhs, Rp, yout,
+                                                                               reinterpret_cast<c128 *>(Y), 0);
+        GSC_HIP(hipGetLastError());
         GSC_HIP(hipStreamSynchronize(st));
         return GSC_OK;
     });

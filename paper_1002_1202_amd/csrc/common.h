@@ -151,6 +151,7 @@ struct Ctx {
     hipStream_t stream = nullptr;
     int num_cu = 256;
     Profiler prof;
+    void *scratch = nullptr;    // device address of the allocation-free scratch array
 };
 
 struct Pair {
