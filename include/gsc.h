@@ -95,7 +95,8 @@ typedef struct {
     int recheck;           /* [0] 1: FP64 true residual of every (k, rhs) into
                               gsc_stats.res_true (full carry only)             */
     int spmm_kernel;       /* [0 = auto = 1] product kernel layout: 1 one block
-                              row x 64 rhs per wave (the only layout)         */
+                              row x 64 rhs per wave (the complex64 steps of
+                              GSC_MIXED: 128 rhs per wave, two per lane)      */
     int inner_method;      /* [0 = auto] inner solver for S r' = r: 1 CG (the
                               first solve always runs CG), 2 Chebyshev on the
                               interval of the first CG solve's Ritz values

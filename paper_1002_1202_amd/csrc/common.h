@@ -178,4 +178,5 @@ inline int div_up(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / 
 
 void ensure_f32(Pair &p);
 
+
 }  // namespace gsc

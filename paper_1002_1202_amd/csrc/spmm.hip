@@ -390,6 +390,126 @@ __global__ __launch_bounds__(kBlock) void k_cheb_mx(
     }
 }
 
+// k_cheb_mx with two columns per lane: a wave covers 128 columns and every
+// gathered load moves 16 bytes per lane (two complex64), half the load
+// instructions per byte of the one-column form.  Same arithmetic per
+// column, same order.
+template <int B, int MODE, int FIN, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_cheb_mx2(
+    int nb, int Rp, int col0, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    const float *__restrict__ Sv, const c64 *__restrict__ y, const c64 *__restrict__ f, c64 *__restrict__ yio,
+    c128 *__restrict__ Y, const c128 *__restrict__ r, const int *__restrict__ skip, float inv_theta, float c1,
+    float c2, double *__restrict__ partial, c128 *__restrict__ dpart, int dot_active_only) {
+    int cx, g;
+    xcd_remap_chunks(cx, g);
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_id();
+    const int col = col0 + cx * 128 + 2 * lane;
+    const bool act0 = !skip[col], act1 = !skip[col + 1];
+    const bool act = act0 || act1;
+    double acc20 = 0.0, acc21 = 0.0;
+    c128 dacc0{0.0, 0.0}, dacc1{0.0, 0.0};
+    const int row_step = kWavesPerBlock * static_cast<int>(gridDim.y);
+    const c64 *x = MODE == 0 ? f : y;
+    if (__ballot(act) != 0) {
+        for (int I = kWavesPerBlock * g + wv; I < nb; I += row_step) {
+            c64 a0[B], a1[B], o0[B], o1[B];
+#pragma unroll
+            for (int a = 0; a < B; ++a) { a0[a] = {0, 0}; a1[a] = {0, 0}; o0[a] = {0, 0}; o1[a] = {0, 0}; }
+            const int b0 = rowptr[I], b1 = rowptr[I + 1];
+            float4 xv[B];
+#pragma unroll
+            for (int c = 0; c < B; ++c) xv[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 2
+            for (int b = b0; b < b1; ++b) {
+                const int J = colidx[b];
+                const float *sb = Sv + static_cast<size_t>(b) * B * B;
+                if (act) {
+#pragma unroll
+                    for (int c = 0; c < B; ++c)
+                        xv[c] = *reinterpret_cast<const float4 *>(x + static_cast<size_t>(J * B + c) * Rp + col);
+                }
+                if (J == I) {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) { o0[c] = {xv[c].x, xv[c].y}; o1[c] = {xv[c].z, xv[c].w}; }
+                }
+#pragma unroll
+                for (int a = 0; a < B; ++a) {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) {
+                        const float sv = sb[a * B + c];
+                        a0[a].re = fmaf(sv, xv[c].x, a0[a].re);
+                        a0[a].im = fmaf(sv, xv[c].y, a0[a].im);
+                        a1[a].re = fmaf(sv, xv[c].z, a1[a].re);
+                        a1[a].im = fmaf(sv, xv[c].w, a1[a].im);
+                    }
+                }
+            }
+            if (!act) continue;
+#pragma unroll
+            for (int a = 0; a < B; ++a) {
+                const size_t e = static_cast<size_t>(I * B + a) * Rp + col;
+                double r20, r21;
+                c64 rv0, rv1;
+                const c64 n0 = cheb_next<float, MODE, false>(o0[a], a0[a], f, yio, e, inv_theta, c1, c2, r20, rv0);
+                const c64 n1 = cheb_next<float, MODE, false>(o1[a], a1[a], f, yio, e + 1, inv_theta, c1, c2, r21, rv1);
+                if (act0) acc20 += r20;
+                if (act1) acc21 += r21;
+                if constexpr (FIN == 0) {
+                    if (act0 && act1) {
+                        *reinterpret_cast<float4 *>(yio + e) = make_float4(n0.re, n0.im, n1.re, n1.im);
+                    } else {
+                        if (act0) yio[e] = n0;
+                        if (act1) yio[e + 1] = n1;
+                    }
+                } else {
+                    if (act0) {
+                        c128 v = ccast<double>(n0);
+                        if constexpr (FIN == 2) v = Y[e] + v;
+                        Y[e] = v;
+                        if constexpr (DOT) dacc0 = dacc0 + v * r[e];
+                    }
+                    if (act1) {
+                        c128 v = ccast<double>(n1);
+                        if constexpr (FIN == 2) v = Y[e + 1] + v;
+                        Y[e + 1] = v;
+                        if constexpr (DOT) dacc1 = dacc1 + v * r[e + 1];
+                    }
+                }
+            }
+        }
+    }
+    __shared__ double red[2][kWavesPerBlock][64];
+    red[0][wv][lane] = acc20;
+    red[1][wv][lane] = acc21;
+    if constexpr (DOT) {
+        __shared__ c128 redc[2][kWavesPerBlock][64];
+        redc[0][wv][lane] = dacc0;
+        redc[1][wv][lane] = dacc1;
+        __syncthreads();
+        if (threadIdx.x < 128) {
+            const int h = threadIdx.x >> 6, ln = threadIdx.x & 63;
+            const int cc = col0 + cx * 128 + 2 * ln + h;
+            if (!skip[cc] || !dot_active_only) {
+                c128 t = redc[h][0][ln];
+#pragma unroll
+                for (int k = 1; k < kWavesPerBlock; ++k) t = t + redc[h][k][ln];
+                dpart[static_cast<size_t>(g) * Rp + cc] = t;
+            }
+        }
+    } else {
+        __syncthreads();
+    }
+    if (threadIdx.x < 128) {
+        const int h = threadIdx.x >> 6, ln = threadIdx.x & 63;
+        const int cc = col0 + cx * 128 + 2 * ln + h;
+        double t = red[h][0][ln];
+#pragma unroll
+        for (int k = 1; k < kWavesPerBlock; ++k) t += red[h][k][ln];
+        partial[static_cast<size_t>(g) * Rp + cc] = t;
+    }
+}
+
 // f = r - S Y in FP64 (S, Y, r in FP64), stored in complex64 as the
 // right-hand side of the next complex64 round; partial ||f||^2.
 template <int B>
@@ -462,10 +582,35 @@ void launch_cheb_mx(hipStream_t st, const Pair &pr, const TileDims &td, int mode
     GSC_REQUIRE(mode >= 0 && mode <= 2 && fin >= 0 && fin <= 2, "bad mixed Chebyshev step");
     GSC_REQUIRE(!dot || (fin > 0 && dpart != nullptr && r != nullptr), "the fused dot needs a final step");
     GSC_REQUIRE(fin == 0 || Y != nullptr, "a final step needs the FP64 solution");
-    dim3 grid(ncols / 64, td.Gs), block(kBlock);
     const float it = static_cast<float>(inv_theta), a = static_cast<float>(c1), b = static_cast<float>(c2);
+    // 128-column pieces with two columns per lane, a 64-column tail with one
+    const int n2 = ncols / 128 * 128;
+    const dim3 block(kBlock);
+    if (n2 > 0) {
+        const dim3 grid(n2 / 128, td.Gs);
+#define GSC_MX(BB, M, F, D)                                                                                    \
+        k_cheb_mx2<BB, M, F, D><<<grid, block, 0, st>>>(td.nb, td.Rp, col0, pr.rowptr.get(), pr.colidx.get(), \
+                                                        Sv, y, f, yio, Y, r, skip, it, a, b, partial, dpart,  \
+                                                        dot_active_only)
+#define GSC_MX_F(BB, M)                                                              \
+    if (fin == 0) { GSC_MX(BB, M, 0, false); }                                       \
+    else if (fin == 1) { if (dot) GSC_MX(BB, M, 1, true); else GSC_MX(BB, M, 1, false); } \
+    else { if (dot) GSC_MX(BB, M, 2, true); else GSC_MX(BB, M, 2, false); }
+#define GSC_MX_B(BB) \
+    if (mode == 0) { GSC_MX_F(BB, 0) } else if (mode == 1) { GSC_MX_F(BB, 1) } else { GSC_MX_F(BB, 2) }
+        if (pr.B == 4) { GSC_MX_B(4) } else { GSC_MX_B(6) }
+#undef GSC_MX_B
+#undef GSC_MX_F
+#undef GSC_MX
+    }
+    if (n2 == ncols) {
+        GSC_HIP(hipGetLastError());
+        return;
+    }
+    const int c0 = col0 + n2;
+    const dim3 grid((ncols - n2) / 64, td.Gs);
 #define GSC_MX(BB, M, F, D)                                                                                      \
-    k_cheb_mx<BB, M, F, D><<<grid, block, 0, st>>>(td.nb, td.Rp, col0, pr.rowptr.get(), pr.colidx.get(), Sv, y, \
+    k_cheb_mx<BB, M, F, D><<<grid, block, 0, st>>>(td.nb, td.Rp, c0, pr.rowptr.get(), pr.colidx.get(), Sv, y,   \
                                                    f, yio, Y, r, skip, it, a, b, partial, dpart, dot_active_only)
 #define GSC_MX_F(BB, M)                                                              \
     if (fin == 0) { GSC_MX(BB, M, 0, false); }                                       \

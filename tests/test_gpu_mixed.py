@@ -129,3 +129,23 @@ def test_mixed_band_energy_and_charge_gradients(ctx, cases):
     assert eH < 1e-9 and eS < 1e-9
     assert rel(cH, oased.gather_blocks(s, rH)) < 1e-9
     assert rel(cS, oased.gather_blocks(s, rS)) < 1e-9
+
+
+@pytest.mark.parametrize("block", [0, 128])
+def test_mixed_two_column_step_and_tail(ctx, block):
+    """The complex64 Chebyshev step runs 128-column pieces with two columns
+    per lane and a 64-column tail with one: 150 rhs (a 192-column tile, its
+    last 42 columns padding), unblocked and in column blocks of 128, against
+    the dense LU at the FP64 bar."""
+    from paper_1002_1202_amd import api
+    c = configs.si_small(cells=(3, 3, 2), n_shift=16, eta=0.05, n_rhs=150, seed=46, vacancy_frac=0.03)
+    s, z, rhs = c["system"], c["z"], c["rhs"]
+    print(f"case: mixed two-column step N={s.n} R={len(rhs)} cheb_block={block}", flush=True)
+    S, H, _ = oased.dense_pair(s)
+    X = ogreen.solve_dense(H, S, z, rhs)
+    pair, _ = api.pair_from_system(ctx, s)
+    res = api.solve(ctx, pair, z, rhs=rhs, tol=1e-12, precision="mixed", cheb_block=block, recheck=True)
+    print(f"  err={rel(res.G_cols, X):.2e} res_true={res.res_true.max():.2e}", flush=True)
+    assert res.status == 0
+    assert rel(res.G_cols, X) < 1e-10
+    assert res.res_true.max() < 1e-10
