@@ -354,11 +354,23 @@ typedef struct {
     int history;          /* [4]    Anderson history (0 = linear mixing)    */
     double tol;           /* [1e-8] max |dq_out - dq_in| to stop            */
     int max_iter;         /* [100]                                          */
+    int neutral;          /* [0] 1: charge neutrality sets the Fermi level
+                             each iteration: E_F solves
+                             -(2/pi) sum_k w_k(E_F) sum_a Im (S G_k)_aa
+                               = sum of the valences
+                             (bisection), with w_k(E_F) the trapezoid
+                             weights over Re z_k truncated at E_F (the
+                             integrand linear between samples); w is then
+                             not used (may be NULL), Re z must increase
+                             and the grid must reach past E_F             */
 } gsc_scc_opts;
 void gsc_scc_opts_default(gsc_scc_opts *o);
+/* e_fermi: HOST, may be NULL; the last E_F in neutral mode (else the top
+ * of the grid, Re z_{nshift-1}).  GSC_E_ARG in neutral mode when Re z is
+ * not increasing or the grid holds fewer electrons than the valences. */
 gsc_status gsc_scc(gsc_ctx *ctx, gsc_csc *csc, gsc_pair *pair, int nshift, const double *z, const double *w,
                    const double *valence, const gsc_scc_opts *sopts, const gsc_opts *opts, double *dq, double *q_orb,
-                   double *e_band, int *iters, double *residual);
+                   double *e_band, int *iters, double *residual, double *e_fermi);
 
 /* Mulliken charge and band energy per orbital a = orb_idx[r] (Sec. 2.2),
  * spin 2, quadrature weights w[k] (HOST) over E_k = Re z_k:

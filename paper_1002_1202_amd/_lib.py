@@ -51,7 +51,8 @@ class Problem(C.Structure):
 
 # exported symbol -> (restype, argtypes)
 class SccOpts(C.Structure):
-    _fields_ = [("beta", C.c_double), ("history", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int)]
+    _fields_ = [("beta", C.c_double), ("history", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
+                ("neutral", C.c_int)]
 
 
 _VP, _DP, _I64P, _I32P = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32)
@@ -88,7 +89,7 @@ SIGNATURES = {
     "gsc_csc_hamiltonian": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int]),
     "gsc_scc_opts_default": (None, [C.POINTER(SccOpts)]),
     "gsc_scc": (C.c_int, [_VP, _VP, _VP, C.c_int, _DP, _DP, _DP, C.POINTER(SccOpts), C.POINTER(Opts), _DP, _DP,
-                          _DP, C.POINTER(C.c_int), _DP]),
+                          _DP, C.POINTER(C.c_int), _DP, _DP]),
     "gsc_lanczos_green": (C.c_int, [_VP, _VP, C.c_int, _DP, C.c_int, _I64P, C.c_int, C.c_double, C.c_int,
                                     C.POINTER(Opts), _VP, _DP, _DP, C.POINTER(C.c_int), C.c_int,
                                     C.POINTER(Stats)]),

@@ -409,26 +409,30 @@ class Csc:
             dq = np.ascontiguousarray(dq, dtype=np.float64)
         L.check(self.ctx.lib.gsc_csc_hamiltonian(self.h, pair.h, _vp(H0), _vp(dq), mem))
 
-    def scc(self, pair: Pair, z, w, valence, dq0=None, beta=0.2, history=4, scc_tol=1e-8, max_iter=100, **opt):
+    def scc(self, pair: Pair, z, w, valence, dq0=None, beta=0.2, history=4, scc_tol=1e-8, max_iter=100,
+            neutral=False, **opt):
         """Self-consistency loop (Anderson mixing) to max |dq_out - dq_in| <=
-        scc_tol; ``opt`` are the solver options of each charge evaluation.
-        Returns a dict with dq, q_orb, e_band, iterations, residual and
-        status; the pair keeps H0 + H^CSC(dq)."""
+        scc_tol; ``opt`` are the solver options of each charge evaluation;
+        ``neutral``: E_F set each iteration by charge neutrality (``w`` not
+        used).  Returns a dict with dq, q_orb, e_band, e_fermi, iterations,
+        residual and status; the pair keeps H0 + H^CSC(dq)."""
         z = np.ascontiguousarray(z, dtype=np.complex128)
-        w = np.ascontiguousarray(w, dtype=np.float64)
+        w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
         valence = np.ascontiguousarray(valence, dtype=np.float64)
         dq = np.zeros(self.n_atoms) if dq0 is None else np.array(dq0, dtype=np.float64)
         q = np.empty(pair.n)
-        so = L.SccOpts(beta, history, scc_tol, max_iter)
+        so = L.SccOpts(beta, history, scc_tol, max_iter, int(neutral))
         opts = make_opts(**opt)
         eb = C.c_double()
         it = C.c_int()
         res = C.c_double()
-        status = self.ctx.lib.gsc_scc(self.ctx.h, self.h, pair.h, z.shape[0], _ptr(_complex_view(z)), _ptr(w),
-                                      _ptr(valence), C.byref(so), C.byref(opts), _ptr(dq), _ptr(q), C.byref(eb),
-                                      C.byref(it), C.byref(res))
+        ef = C.c_double()
+        status = self.ctx.lib.gsc_scc(self.ctx.h, self.h, pair.h, z.shape[0], _ptr(_complex_view(z)),
+                                      None if w is None else _ptr(w), _ptr(valence), C.byref(so), C.byref(opts),
+                                      _ptr(dq), _ptr(q), C.byref(eb), C.byref(it), C.byref(res), C.byref(ef))
         L.check(status)
-        return dict(dq=dq, q_orb=q, e_band=eb.value, iterations=it.value, residual=res.value, status=status)
+        return dict(dq=dq, q_orb=q, e_band=eb.value, e_fermi=ef.value, iterations=it.value, residual=res.value,
+                    status=status)
 
 
 @dataclass

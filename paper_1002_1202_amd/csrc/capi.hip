@@ -67,6 +67,43 @@ __global__ void k_mulliken(int K, int R, const c128 *sg, size_t ld_k, size_t ld_
     e[r] = f * ae;
 }
 
+// t_k = sum_a Im (S G_k)_aa over the R orbitals of shift k (one block per k)
+__global__ void k_sg_trace(int R, const c128 *sg, double *t) {
+    __shared__ double lds[256];
+    const int k = blockIdx.x;
+    double s = 0.0;
+    for (int a = threadIdx.x; a < R; a += 256) s += sg[static_cast<size_t>(k) * R + a].im;
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) lds[threadIdx.x] += lds[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) t[k] = lds[0];
+}
+
+// Trapezoid weights over the ascending grid E truncated at ef, with the
+// integrand linear between samples: sum_k w_k f(E_k) is the integral of the
+// interpolant from E_0 to ef.
+void truncated_trapezoid(const std::vector<double> &E, double ef, std::vector<double> &w) {
+    const size_t K = E.size();
+    w.assign(K, 0.0);
+    for (size_t j = 0; j + 1 < K && ef > E[j]; ++j) {
+        const double h = E[j + 1] - E[j];
+        const double d = std::min(ef - E[j], h);
+        w[j] += d - 0.5 * d * d / h;
+        w[j + 1] += 0.5 * d * d / h;
+    }
+}
+
+double electron_count(const std::vector<double> &E, const std::vector<double> &t, double ef,
+                      std::vector<double> &w) {
+    truncated_trapezoid(E, ef, w);
+    double s = 0.0;
+    for (size_t k = 0; k < E.size(); ++k) s += w[k] * t[k];
+    return -2.0 / M_PI * s;
+}
+
 __global__ void k_sum(int n, const double *v, double *out) {
     __shared__ double lds[256];
     double s = 0.0;
@@ -143,6 +180,32 @@ __global__ void k_noalloc_cols(int R, int Rp, c128 *z, int *seed) {
     if (c >= Rp) return;
     seed[c] = c;
     if (c >= R) z[c] = c128{0.0, 0.0};
+}
+
+// (S G_k)_aa for the unit right-hand sides e_a, a = orb_idx[r], into the
+// device array sg [nshift][norb]: the projected solve carrying c = S e_a,
+// or the full carry's columns projected on S e_a.
+gsc_status sg_solve(Ctx &ctx, const Pair &p, int nshift, const double *z, int norb, const int64_t *orb_idx,
+                    const gsc_opts &o, c128 *sg, gsc_stats *stats) {
+    SolveRequest req;
+    req.pair = &p;
+    req.K = nshift;
+    req.z = z;
+    req.R = norb;
+    req.rhs_idx = orb_idx;
+    req.opts = o;
+    req.out_mem = GSC_MEM_DEVICE;
+    req.stats = stats;
+    ProjSpec ps;
+    if (o.carry == GSC_CARRY_FULL) {
+        req.sg_diag = sg;
+    } else {
+        ps.M = 0;
+        ps.srow = true;
+        req.proj = &ps;
+        req.proj_out = sg;
+    }
+    return run_solve(ctx, req);
 }
 
 void validate_opts(const gsc_opts &o) {
@@ -684,19 +747,22 @@ void gsc_scc_opts_default(gsc_scc_opts *o) {
     o->history = 4;
     o->tol = 1e-8;
     o->max_iter = 100;
+    o->neutral = 0;
 }
 
 gsc_status gsc_scc(gsc_ctx *ctx, gsc_csc *csc, gsc_pair *pair, int nshift, const double *z, const double *w,
                    const double *valence, const gsc_scc_opts *sopts, const gsc_opts *opts, double *dq, double *q_orb,
-                   double *e_band, int *iters, double *residual) {
+                   double *e_band, int *iters, double *residual, double *e_fermi) {
     return guarded([&] {
         GSC_REQUIRE(ctx != nullptr && csc != nullptr && pair != nullptr, "ctx/csc/pair must not be NULL");
-        GSC_REQUIRE(w != nullptr && valence != nullptr && dq != nullptr, "w/valence/dq must not be NULL");
         gsc_scc_opts so;
         gsc_scc_opts_default(&so);
         if (sopts) so = *sopts;
-        GSC_REQUIRE(so.beta > 0.0 && so.history >= 0 && so.history <= 16 && so.tol > 0.0 && so.max_iter >= 1,
+        GSC_REQUIRE(so.beta > 0.0 && so.history >= 0 && so.history <= 16 && so.tol > 0.0 && so.max_iter >= 1 &&
+                        (so.neutral == 0 || so.neutral == 1),
                     "invalid scc options");
+        GSC_REQUIRE((w != nullptr || so.neutral) && valence != nullptr && dq != nullptr,
+                    "w/valence/dq must not be NULL");
         gsc_opts o;
         gsc_opts_default(&o);
         if (opts) o = *opts;
@@ -719,14 +785,54 @@ gsc_status gsc_scc(gsc_ctx *ctx, gsc_csc *csc, gsc_pair *pair, int nshift, const
         GSC_HIP(hipMemcpyAsync(Z.get(), valence, na * 8, hipMemcpyHostToDevice, st));
         std::vector<int64_t> orbs(N);
         for (int64_t i = 0; i < N; ++i) orbs[i] = i;
+        // neutral mode: the grid's real parts, the valence count and the
+        // per-shift projections (S G_k)_aa kept for the weights chosen after
+        std::vector<double> E(nshift), t(nshift), wk;
+        double ne = 0.0, ef = z[2 * (nshift - 1)];
+        for (int k = 0; k < nshift; ++k) E[k] = z[2 * k];
+        DevBuf<c128> sg, dz;
+        DevBuf<double> tdev, dw, de, deb;
+        if (so.neutral) {
+            for (int k = 1; k < nshift; ++k) GSC_REQUIRE(E[k] > E[k - 1], "neutral mode needs increasing Re z");
+            for (int64_t a = 0; a < na; ++a) ne += valence[a];
+            GSC_REQUIRE(ne > 0.0, "neutral mode needs a positive valence count");
+            sg.alloc(static_cast<size_t>(nshift) * N);
+            dz.alloc(nshift); tdev.alloc(nshift); dw.alloc(nshift); de.alloc(N); deb.alloc(1);
+            GSC_HIP(hipMemcpyAsync(dz.get(), z, nshift * sizeof(c128), hipMemcpyHostToDevice, st));
+        }
         int it = 0, stored = 0;
         double res = 0.0, eb = 0.0;
         for (it = 1; it <= so.max_iter; ++it) {
             csc_potential(c, din.get(), V.get(), st);
             csc_hamiltonian(c, p, H0.get(), V.get(), st);
-            const gsc_status s = gsc_mulliken_band(ctx, pair, nshift, z, w, static_cast<int>(N), orbs.data(), &o,
-                                                   qorb.get(), nullptr, &eb, GSC_MEM_DEVICE, nullptr);
-            if (s < 0) return s;
+            if (so.neutral) {
+                const gsc_status s = sg_solve(ctx->c, p, nshift, z, static_cast<int>(N), orbs.data(), o, sg.get(),
+                                              nullptr);
+                if (s < 0) return s;
+                k_sg_trace<<<nshift, 256, 0, st>>>(static_cast<int>(N), sg.get(), tdev.get());
+                GSC_HIP(hipMemcpyAsync(t.data(), tdev.get(), nshift * 8, hipMemcpyDeviceToHost, st));
+                GSC_HIP(hipStreamSynchronize(st));
+                // E_F by bisection: the count grows with E_F (-Im Tr S G > 0)
+                double lo = E.front(), hi = E.back();
+                GSC_REQUIRE(electron_count(E, t, hi, wk) >= ne, "the shift grid does not hold the electrons");
+                while (hi - lo > 1e-13 * std::max(1.0, std::fabs(lo) + std::fabs(hi))) {
+                    const double mid = 0.5 * (lo + hi);
+                    if (electron_count(E, t, mid, wk) < ne) lo = mid;
+                    else hi = mid;
+                }
+                ef = 0.5 * (lo + hi);
+                truncated_trapezoid(E, ef, wk);
+                GSC_HIP(hipMemcpyAsync(dw.get(), wk.data(), nshift * 8, hipMemcpyHostToDevice, st));
+                k_mulliken<<<div_up(N, 256), 256, 0, st>>>(nshift, static_cast<int>(N), sg.get(), N, 1, dz.get(),
+                                                           dw.get(), qorb.get(), de.get());
+                k_sum<<<1, 256, 0, st>>>(static_cast<int>(N), de.get(), deb.get());
+                GSC_HIP(hipGetLastError());
+                GSC_HIP(hipMemcpyAsync(&eb, deb.get(), 8, hipMemcpyDeviceToHost, st));
+            } else {
+                const gsc_status s = gsc_mulliken_band(ctx, pair, nshift, z, w, static_cast<int>(N), orbs.data(), &o,
+                                                       qorb.get(), nullptr, &eb, GSC_MEM_DEVICE, nullptr);
+                if (s < 0) return s;
+            }
             csc_charges(c, qorb.get(), Z.get(), din.get(), dout.get(), f.get(), st);
             max_abs(na, f.get(), mx.get(), st);
             GSC_HIP(hipMemcpyAsync(&res, mx.get(), 8, hipMemcpyDeviceToHost, st));
@@ -787,6 +893,7 @@ gsc_status gsc_scc(gsc_ctx *ctx, gsc_csc *csc, gsc_pair *pair, int nshift, const
         if (e_band) *e_band = eb;
         if (iters) *iters = conv ? it : so.max_iter;
         if (residual) *residual = res;
+        if (e_fermi) *e_fermi = ef;
         return conv ? GSC_OK : GSC_NOT_CONVERGED;
     });
 }
@@ -807,26 +914,8 @@ gsc_status gsc_mulliken_band(gsc_ctx *ctx, const gsc_pair *pair, int nshift, con
         for (int r = 0; r < norb; ++r) GSC_REQUIRE(orb_idx[r] >= 0 && orb_idx[r] < p.n, "orbital index out of range");
         DeviceGuard g(ctx->c.device);
         hipStream_t st = ctx->c.stream;
-        SolveRequest req;
-        req.pair = &p;
-        req.K = nshift;
-        req.z = z;
-        req.R = norb;
-        req.rhs_idx = orb_idx;
-        req.opts = o;
-        req.out_mem = GSC_MEM_DEVICE;
-        req.stats = stats;
         DevBuf<c128> sg(static_cast<size_t>(nshift) * norb);
-        ProjSpec ps;
-        if (o.carry == GSC_CARRY_FULL) {
-            req.sg_diag = sg.get();
-        } else {
-            ps.M = 0;
-            ps.srow = true;
-            req.proj = &ps;
-            req.proj_out = sg.get();
-        }
-        const gsc_status s = run_solve(ctx->c, req);
+        const gsc_status s = sg_solve(ctx->c, p, nshift, z, norb, orb_idx, o, sg.get(), stats);
         DevBuf<c128> dz(nshift);
         DevBuf<double> dw(nshift), dq(norb), de(norb), deb(1);
         GSC_HIP(hipMemcpyAsync(dz.get(), z, nshift * sizeof(c128), hipMemcpyHostToDevice, st));

@@ -2025,12 +2025,16 @@ template <typename T> class TileSolver {
         return changed;
     }
 
-    // Rounds of the mixed inner solve for a relative tolerance tau: each
-    // complex64 round reduces its right-hand side to at most kMxFloor (well
-    // above what FP32 arithmetic resolves), the FP64 residual between rounds
-    // carries the rest; entries are the step counts K_j of the rounds.
+    // Rounds of the mixed inner solve for a relative tolerance tau: one
+    // round when tau >= kMxSingle (a few times what the FP32 residual
+    // estimate resolves), else rounds that each reduce their right-hand side
+    // to kMxFloor, the FP64 residual between rounds carrying the rest;
+    // entries are the step counts K_j of the rounds.
     std::vector<int> mx_plan_for(double tau) const {
         std::vector<int> plan;
+        // down to kMxSingle one complex64 round is cheaper than two rounds
+        // and an FP64 residual pass
+        if (tau >= kMxSingle) return {cheb_steps_for(tau)};
         double rem = tau;
         while (true) {
             plan.push_back(cheb_steps_for(std::max(rem, kMxFloor)));
@@ -2299,6 +2303,7 @@ template <typename T> class TileSolver {
     DevBuf<c64> mx_f_, mx_ya_, mx_yb_;
     std::vector<int> mx_plan_;
     static constexpr double kMxFloor = 1e-5;
+    static constexpr double kMxSingle = 2e-6;
     static constexpr int kMxSafetySteps = 4;
     long long cheb_extra_ = 0;
     long long inner_total_ = 0;

@@ -97,3 +97,32 @@ def test_csc_errors(ctx):
     U[1] = 0.0
     with pytest.raises(_lib.GscError):
         api.Csc(ctx, pair, s, U)
+
+
+@pytest.mark.parametrize("n_mol", [4, 24])
+def test_scc_neutral_vs_oracle(ctx, n_mol):
+    """The loop with the Fermi level set each iteration by charge
+    neutrality (trapezoid weights truncated at E_F) against the oracle's
+    loop: the same charges, E_F and band energy, and sum dq = 0."""
+    from paper_1002_1202_amd import api
+    s = configs.water_small(n_mol=n_mol, n_rhs=4)["system"]
+    S, H0, _ = oased.dense_pair(s)
+    z = shift_grid(-60.0, 5.0, 128, 0.5)
+    print(f"case: neutral scc water{n_mol} N={s.n}", flush=True)
+    U = hubbard_u(s)
+    G = ocsc.gamma_matrix(s, U)
+    dq_ref, q_ref, eb_ref, it_ref, res_ref, ef_ref = ocsc.scc(s, S, H0, G, z, None, beta=0.2, tol=1e-9,
+                                                              max_iter=300, history=6, neutral=True)
+    assert res_ref <= 1e-9
+    pair, _ = api.pair_from_system(ctx, s)
+    cs = api.Csc(ctx, pair, s, U)
+    out = cs.scc(pair, z, None, s.valence, beta=0.2, history=6, scc_tol=1e-9, max_iter=300, neutral=True,
+                 tol=1e-12)
+    print(f"  iterations gpu {out['iterations']} oracle {it_ref}; E_F {out['e_fermi']:.6f} vs {ef_ref:.6f}; "
+          f"|dq - ref| {np.abs(out['dq'] - dq_ref).max():.1e}; sum dq {out['dq'].sum():.1e}", flush=True)
+    assert out["status"] == 0 and out["residual"] <= 1e-9
+    np.testing.assert_allclose(out["dq"], dq_ref, atol=2e-8)
+    np.testing.assert_allclose(out["q_orb"], q_ref, atol=2e-8)
+    assert out["e_fermi"] == pytest.approx(ef_ref, abs=1e-8)
+    assert out["e_band"] == pytest.approx(eb_ref, rel=1e-8)
+    assert abs(out["dq"].sum()) < 1e-8

@@ -244,3 +244,29 @@ def test_ring_copy_by_transpose_kernel():
     print(f"  wide vs 256-column tiles {d:.2e}, sampled true residual {worst:.2e}", flush=True)
     assert d < 1e-8          # both converged to tol 1e-10; a wrong copy gives O(1)
     assert worst < 1e-8
+
+
+@pytest.mark.parametrize("prec,carry", [("fp64", "full"), ("mixed", "projected")])
+def test_breakdown_status(ctx, prec, carry):
+    """COCG breakdown (the unconjugated r'^T r vanishing) is reported as
+    GSC_E_BREAKDOWN: S = I, a right-hand side b = (1, i, 0, 0) has
+    b^T b = 1 + i^2 = 0 exactly, so rho_0 = r'^T r = b^T b = 0 with shifts
+    still to converge; a second, ordinary right-hand side in the same call
+    does not hide it.  A plain b = (1, 2, 0, 0) on the same pair solves."""
+    from paper_1002_1202_amd import _lib, api
+    print(f"case: forced breakdown {prec} {carry}", flush=True)
+    pair, eps = diagonal_pair(ctx, 2, 4, seed=7)
+    n = 8
+    z = shift_grid(-20.0, 0.0, 5, 0.1)
+    B = np.zeros((2, n), complex)
+    B[0, 0], B[0, 1] = 1.0, 1j
+    B[1, 2], B[1, 5] = 1.0, -0.5
+    kw = dict(carry=carry, proj=np.zeros((2, 1), np.int64)) if carry == "projected" else {}
+    with pytest.raises(_lib.GscError) as ei:
+        api.solve(ctx, pair, z, B=B, tol=1e-10, precision=prec, **kw)
+    assert ei.value.status == -4, ei.value
+    good = np.zeros((1, n), complex)
+    good[0, 0], good[0, 1] = 1.0, 2.0
+    res = api.solve(ctx, pair, z, B=good, tol=1e-12, precision=prec)
+    ref = good[0][None, :] / (z[:, None] - eps[None, :])
+    assert rel(res.G_cols[:, 0, :], ref) < 1e-11

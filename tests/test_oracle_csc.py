@@ -85,3 +85,66 @@ def test_mixing_fixed_point_matches_root_finder():
     np.testing.assert_allclose(dq2, root.x, atol=1e-9)
     # charge flows from the hydrogens to the oxygen of every molecule
     assert (dq[0::3] > 0).all() and (dq[1::3] < 0).all() and (dq[2::3] < 0).all()
+
+
+def test_truncated_weights_integrate_lines_exactly():
+    """The weights truncated at E_F integrate any function that is linear
+    between the samples exactly from E_0 to E_F (closed form for 1 and E on
+    a non-uniform grid), reduce to the full trapezoid rule at the top of the
+    grid, vanish below it and are continuous through the samples."""
+    rng = np.random.default_rng(5)
+    E = np.sort(rng.uniform(-30.0, 5.0, 40))
+    for ef in np.concatenate([rng.uniform(E[0], E[-1], 25), E[[3, 17, 39]]]):
+        w = csc.truncated_weights(E, ef)
+        assert w @ np.ones_like(E) == pytest.approx(ef - E[0], abs=1e-12)
+        assert w @ E == pytest.approx(0.5 * (ef * ef - E[0] ** 2), abs=1e-10)
+        a, b = rng.normal(size=2)
+        j = np.searchsorted(E, ef, side="right") - 1
+        if j < len(E) - 1:   # a piecewise-linear f: integral segment by segment
+            f = a * E + b * np.abs(E - E[j])
+            fe = np.interp(ef, E, f)
+            ref = np.trapezoid(f[:j + 1], E[:j + 1]) + 0.5 * (ef - E[j]) * (f[j] + fe)
+            assert w @ f == pytest.approx(ref, abs=1e-10)
+    z = shift_grid(-20.0, 5.0, 33, 0.1)
+    np.testing.assert_allclose(csc.truncated_weights(z.real, z.real[-1]), trapezoid_weights(z), atol=1e-14)
+    assert not csc.truncated_weights(E, E[0] - 1.0).any()
+    for k in (5, 20):
+        lo = csc.truncated_weights(E, E[k] - 1e-12)
+        hi = csc.truncated_weights(E, E[k] + 1e-12)
+        np.testing.assert_allclose(lo, hi, atol=1e-10)
+
+
+def test_fermi_level_matches_root_finder():
+    """Bisection for the neutral E_F agrees with Brent's method on the same
+    electron count, on a water system's actual (S G)_aa traces."""
+    s, S, H0, _, _ = _water_scc_case(3)
+    z = shift_grid(-60.0, 5.0, 200, 0.3)
+    from oracle import green
+    X = green.solve_dense(H0, S, z, np.arange(s.n))
+    t = np.einsum("ij,kji->ki", S, X).imag.sum(axis=1)
+    ne = float(s.valence.sum())
+    ef = csc.fermi_level(z.real, t, ne)
+    ref = scipy.optimize.brentq(lambda e: csc.electron_count(z.real, t, e) - ne, z.real[0], z.real[-1],
+                                xtol=1e-14)
+    assert ef == pytest.approx(ref, abs=1e-10)
+    assert csc.electron_count(z.real, t, ef) == pytest.approx(ne, abs=1e-9)
+    with pytest.raises(ValueError):
+        csc.fermi_level(z.real, t, 10 * ne)
+
+
+def test_neutral_scc_fixed_point_matches_root_finder():
+    """The loop with E_F set by neutrality converges to the root of the
+    neutral charge map (an independent solver) and its charges sum to the
+    valence count (sum dq = 0)."""
+    s, S, H0, _, _ = _water_scc_case(4)
+    z = shift_grid(-60.0, 5.0, 160, 0.5)
+    G = csc.gamma_matrix(s, hubbard_u(s))
+    dq, q, eb, it, res, ef = csc.scc(s, S, H0, G, z, None, beta=0.2, tol=1e-11, max_iter=300, history=4,
+                                     neutral=True)
+    assert res <= 1e-11
+    assert abs(dq.sum()) < 1e-9 and q.sum() == pytest.approx(s.valence.sum(), abs=1e-9)
+    F = lambda x: csc.charge_response_neutral(s, S, H0, G, z, x)[0] - x   # noqa: E731
+    root = scipy.optimize.root(F, np.zeros(s.n_atoms), tol=1e-13)
+    assert root.success
+    np.testing.assert_allclose(dq, root.x, atol=1e-8)
+    assert z.real[0] < ef < z.real[-1]
