@@ -521,6 +521,53 @@ def batched_compare(ctx, copy_gbs=None):
     return out
 
 
+def member_measure(ctx, index, precision, tol=1e-6, relax=False):
+    """One member of the 32-system batch alone (projected carry, G_jj and
+    the S e_j projection, tol 1e-6), one warm-up and one timed solve with
+    every kernel timed by HIP events on the library's stream: per-kernel
+    algorithmic GB/s and the dominant kernel's roofline.  The largest
+    member (index 31, N = 131072) has streamed vectors far beyond the 256 MB
+    infinity cache."""
+    import torch
+
+    from paper_1002_1202_amd import api
+    from synth import configs
+
+    it = configs.batch32()["items"][index]
+    s, z, rhs = it["system"], it["z"], it["rhs"]
+    pair, _ = api.pair_from_system(ctx, s)
+    kw = dict(tol=tol, precision=precision, carry="projected", proj=rhs[:, None], inner_relax=relax)
+    api.solve(ctx, pair, z, rhs=rhs, max_iter=3, **kw)
+    api.profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = api.solve(ctx, pair, z, rhs=rhs, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    p = api.profile_read(ctx)
+    api.profile_enable(ctx, False)
+    dom = max(p, key=lambda k: p[k][0])
+    ms, n, by = p[dom]
+    copy_gbs = copy_bandwidth()
+    achieved = by / (ms * 1e-3) / 1e9
+    from paper_1002_1202_amd import rocprof_summary
+    traffic = None
+    if dom in rocprof_summary.KERNEL_SOURCES:
+        traffic = rocprof_summary.read_traffic(
+            os.path.join(ROOT, "profiles", f"batch32_member{index}_{dom}_traffic.md"), dom)
+    return {"workload": f"batch32 member {index}: N={s.n}, K={len(z)}, R={len(rhs)}, projected carry",
+            "precision": precision, "tol": tol, "inner_relax": relax, "seconds": dt,
+            "value": r.shift_rhs_iters / dt, "unit": UNIT, "outer_iters": r.outer_iters,
+            "inner_iters": r.inner_iters,
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "copy_gbs_measured": copy_gbs,
+                         "frac_of_copy": achieved / copy_gbs, "bytes_per_launch": by / max(n, 1),
+                         "avg_launch_ms": ms / max(n, 1), "traffic": traffic},
+            "kernels": {k: {"ms": round(v[0], 3), "launches": v[1], "GB": round(v[2] / 1e9, 3),
+                            "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
+                        for k, v in p.items() if v[1] > 0}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -537,7 +584,9 @@ def main():
     ap.add_argument("--inner", type=int, default=0, help="0 auto, 1 CG, 2 Chebyshev")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate launch shapes on this problem first and use the fastest")
-    ap.add_argument("--only", default=None, choices=["batched", "lanczos"],
+    ap.add_argument("--member", type=int, default=31,
+                    help="with --only member: the batch32 member (default 31, the largest)")
+    ap.add_argument("--only", default=None, choices=["batched", "lanczos", "member"],
                     help="instead of the throughput line: only the batched mixed-vs-FP64 comparison or only "
                          "the Lanczos-vs-COCG comparison (its own JSON line; for per-workload profiles)")
     ap.add_argument("--forces", default=None, choices=["slab8192", "water3000"],
@@ -589,6 +638,10 @@ def main():
         return
     if args.only == "batched":
         print(json.dumps(batched_compare(api.Context(0))), flush=True)
+        return
+    if args.only == "member":
+        print(json.dumps(member_measure(api.Context(0), args.member, args.precision, tol=args.tol or 1e-6)),
+              flush=True)
         return
     if args.only == "lanczos":
         print(json.dumps(lanczos_compare(api.Context(0), workload(args.workload))), flush=True)
@@ -658,7 +711,7 @@ def main():
     achieved = (byts / (ms * 1e-3)) / 1e9 if ms > 0 else 0.0
     from paper_1002_1202_amd import rocprof_summary
     traffic = None
-    if dom in rocprof_summary.KERNEL_SOURCES and args.precision == "fp64":
+    if dom in rocprof_summary.KERNEL_SOURCES:
         traffic = rocprof_summary.read_traffic(
             os.path.join(ROOT, "profiles", f"{cfg['name']}_{dom}_traffic.md"), dom)
     copy_gbs = copy_bandwidth()

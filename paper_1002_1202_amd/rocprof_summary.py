@@ -4,6 +4,8 @@ Two summaries, both Markdown with the command that produced the data:
 
 ``stats``    the ``--kernel-trace --stats`` CSV as a table (calls, total,
              average, min and max duration per kernel).
+``counters`` per-dispatch means of the counters of several ``--pmc`` runs for
+             the kernels matching a pattern, one row per kernel.
 ``traffic``  HBM bytes per dispatch of one kernel from two ``--pmc`` runs
              (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch), each scaled
              by what the same counter reads for a plain copy-like kernel of
@@ -13,6 +15,7 @@ Two summaries, both Markdown with the command that produced the data:
              counters still describe the current kernel.
 
     python -m paper_1002_1202_amd.rocprof_summary stats STATS_CSV --title T --cmd C
+    python -m paper_1002_1202_amd.rocprof_summary counters DIR [DIR ...] --kernel REGEX --title T --cmd C
     python -m paper_1002_1202_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR \
         --kernel REGEX --name NAME --probe-bytes B --cmd-fetch C1 --cmd-write C2
 """
@@ -30,6 +33,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # sources whose change invalidates a traffic summary of a product kernel
 KERNEL_SOURCES = {
     "cheb_step": ["csrc/spmm.hip", "csrc/kernels.h"],
+    "cheb_mx": ["csrc/spmm.hip", "csrc/kernels.h"],
     "shift_update": ["csrc/solver.hip", "csrc/kernels.h"],
 }
 
@@ -108,6 +112,31 @@ def traffic_md(fetch_dir, write_dir, kernel, name, probe_bytes, cmd_fetch, cmd_w
     return "\n".join(out)
 
 
+def counters_md(dirs, kernel, title, cmds):
+    """Mean value per dispatch of every counter found under the run
+    directories, for each kernel (short name) matching the pattern."""
+    rx = re.compile(kernel)
+    acc = {}
+    for d in dirs:
+        per = {}
+        for r in _counter_rows(d):
+            if not rx.search(r["Kernel_Name"]):
+                continue
+            key = (_short(r["Kernel_Name"]), r["Counter_Name"], r.get("Dispatch_Id") or r.get("Correlation_Id"))
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        for (k, c, _), v in per.items():
+            acc.setdefault(k, {}).setdefault(c, []).append(v)
+    names = sorted({c for d in acc.values() for c in d})
+    out = [f"# {title}", "", "Commands (MI355X, from the repository root; one --pmc run per line):", "", "```",
+           *cmds, "```", "", "Mean per dispatch.", "",
+           "| kernel | dispatches | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
+    for k in sorted(acc):
+        n = max(len(v) for v in acc[k].values())
+        cells = [f"{sum(acc[k][c]) / len(acc[k][c]):.4g}" if c in acc[k] else "" for c in names]
+        out.append(f"| `{k}` | {n} | " + " | ".join(cells) + " |")
+    return "\n".join(out)
+
+
 def read_traffic(path: str, name: str):
     """traffic_bytes_per_dispatch recorded in a traffic summary, or None when
     the file is missing, names another kernel or its source digest no longer
@@ -129,6 +158,11 @@ def main(argv=None):
     s.add_argument("csv")
     s.add_argument("--title", required=True)
     s.add_argument("--cmd", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--cmd", action="append", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
@@ -141,6 +175,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.mode == "stats":
         print(stats_md(a.csv, a.title, a.cmd))
+    elif a.mode == "counters":
+        print(counters_md(a.dirs, a.kernel, a.title, a.cmd))
     else:
         print(traffic_md(a.fetch_dir, a.write_dir, a.kernel, a.name, a.probe_bytes, a.cmd_fetch, a.cmd_write,
                          a.probe))
