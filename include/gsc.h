@@ -131,6 +131,19 @@ typedef struct {
     int batch_streams;     /* [0 = auto = 8] gsc_solve_batched: jobs (system,
                               rhs tile) iterating concurrently, each on its
                               own stream                                      */
+    int batch_mem_mb;      /* [0 = auto] gsc_solve_batched: device memory (MiB)
+                              that the workspaces of the jobs iterating at
+                              once may hold together.  Jobs start longest
+                              first; a job starts when its workspace fits
+                              beside those of the live jobs (a job always
+                              starts when none is live), and the workspaces
+                              of finished jobs are released when a starting
+                              job needs their room (else at the end).  auto =
+                              80 % of the device memory free at the call.    */
+    int row_groups;        /* [0 = auto] workgroup rows of the product and
+                              Chebyshev launches (a multiple of 8, at most
+                              65528; capped at one block row per wave);
+                              auto from the launch width                      */
     int reserved[1];
 } gsc_opts;
 

@@ -23,7 +23,8 @@ class Opts(C.Structure):
                 ("seed_index", C.c_int), ("fuse_steps", C.c_int), ("rhs_tile", C.c_int),
                 ("recheck", C.c_int), ("spmm_kernel", C.c_int), ("inner_method", C.c_int),
                 ("graph_iters", C.c_int), ("stream_hint", C.c_int), ("cheb_block", C.c_int),
-                ("inner_relax", C.c_int), ("batch_streams", C.c_int), ("reserved", C.c_int * 1)]
+                ("inner_relax", C.c_int), ("batch_streams", C.c_int), ("batch_mem_mb", C.c_int),
+                ("row_groups", C.c_int), ("reserved", C.c_int * 1)]
 
 
 class Stats(C.Structure):

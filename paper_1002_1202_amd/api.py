@@ -213,7 +213,7 @@ def spmm_noalloc(ctx: Context, pair: Pair, X, alpha_S, Y=None):
 def make_opts(tol=1e-10, max_iter=5000, inner_tol=0.0, inner_max_iter=200, precision="fp64",
               carry="full", seed_index=-1, fuse_steps=0, rhs_tile=0, recheck=False,
               spmm_kernel=0, inner_method=0, graph_iters=0, stream_hint=0, cheb_block=0,
-              inner_relax=False, batch_streams=0) -> L.Opts:
+              inner_relax=False, batch_streams=0, batch_mem_mb=0, row_groups=0) -> L.Opts:
     """gsc_opts with the library's defaults for every option not given (the
     fields and their meaning are those of gsc_opts in include/gsc.h).
     ``precision``: "fp64"; "mixed" (FP64 seed process, inner S-solve in
@@ -236,6 +236,8 @@ def make_opts(tol=1e-10, max_iter=5000, inner_tol=0.0, inner_max_iter=200, preci
     o.cheb_block = cheb_block
     o.inner_relax = int(inner_relax)
     o.batch_streams = batch_streams
+    o.batch_mem_mb = batch_mem_mb
+    o.row_groups = row_groups
     return o
 
 

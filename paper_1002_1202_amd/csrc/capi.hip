@@ -220,6 +220,9 @@ void validate_opts(const gsc_opts &o) {
     GSC_REQUIRE(o.cheb_block >= 0 && o.cheb_block % 64 == 0, "cheb_block must be 0 or a multiple of 64");
     GSC_REQUIRE(o.inner_relax == 0 || o.inner_relax == 1, "inner_relax must be 0 or 1");
     GSC_REQUIRE(o.inner_method >= 0 && o.inner_method <= 2, "inner_method must be 0, 1 or 2");
+    GSC_REQUIRE(o.row_groups >= 0 && o.row_groups % 8 == 0 && o.row_groups <= 65528,
+                "row_groups must be 0 or a multiple of 8 up to 65528");
+    GSC_REQUIRE(o.batch_mem_mb >= 0, "batch_mem_mb must not be negative");
 }
 
 void validate_shifts(int nshift, const double *z, int seed_index) {

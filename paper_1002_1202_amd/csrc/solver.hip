@@ -1408,6 +1408,11 @@ template <typename T> class TileSolver {
             if (huge) cb = 64;
             td.cb = (cb >= 64 && cb < Rp) ? cb : Rp;
             set_spmm_geometry(td, pr_);
+            if (req.opts.row_groups > 0) {
+                // caller's row groups, at most one block row per wave
+                const int cap = (td.nb + 3) / 4;
+                td.Gs = (std::min(req.opts.row_groups, cap) + 7) / 8 * 8;
+            }
             td.nt = req.opts.stream_hint == 2 || (req.opts.stream_hint == 0 && huge);
         }
         st_ = ctx_.stream;
@@ -2464,6 +2469,10 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
     }
     std::stable_sort(jobs.begin(), jobs.end(), [](const BatchJob &a, const BatchJob &b) { return a.work > b.work; });
     const int ns = std::max(1, std::min<int>(max_streams, static_cast<int>(jobs.size())));
+    // device memory the live jobs' workspaces may hold together
+    const int mem_mb = reqs.front().opts.batch_mem_mb;
+    double budget = mem_mb > 0 ? static_cast<double>(mem_mb) * 1048576.0
+                               : 0.8 * static_cast<double>(dev_usable_bytes());
     std::vector<hipStream_t> streams(ns);
     for (auto &st : streams) GSC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     struct Live {
@@ -2475,10 +2484,10 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
         hipEvent_t ev = nullptr;
         DevBuf<Status> dstat;
         Status *hstat = nullptr;
-        int n = 0;
+        int n = 0, stream = -1;
         long long col_iters = 0;            // column-iterations accounted so far
-        double bytes = 0.0, bytes_inner = 0.0;
-        bool inflight = false, finished = false, graphed = false;
+        double bytes = 0.0, bytes_inner = 0.0, ws = 0.0;
+        bool inflight = false, finished = false, graphed = false, held = false;
         gsc_opts o{};
     };
     std::vector<Live> live(jobs.size());
@@ -2490,16 +2499,54 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
         GSC_HIP(hipGraphInstantiate(&L.exec, L.graph, nullptr, nullptr, 0));
         L.ts->set_inner_total(counted);
     };
+    // the handles of a job; its workspace (the tile solver's vectors) is
+    // released separately
+    auto drop_handles = [](Live &L) {
+        if (L.exec) (void)hipGraphExecDestroy(L.exec);
+        if (L.graph) (void)hipGraphDestroy(L.graph);
+        if (L.ev) (void)hipEventDestroy(L.ev);
+        if (L.hstat) (void)hipHostFree(L.hstat);
+        L.exec = nullptr;
+        L.graph = nullptr;
+        L.ev = nullptr;
+        L.hstat = nullptr;
+    };
+    auto release_workspace = [](Live &L) {
+        L.ts.reset();
+        L.dz.release();
+        L.drhs.release();
+        L.dstat.release();
+        L.held = false;
+    };
+    // estimated device bytes of a job's workspace: the tile's vectors and
+    // the per-(shift, column) scalars, coefficients and projections
+    auto job_bytes = [](const BatchJob &jb) {
+        const SolveRequest &rq = *jb.req;
+        const double Rp = (jb.R + 63) / 64 * 64;
+        const double NR = static_cast<double>(rq.pair->n) * Rp;
+        const bool mx = std::is_same<T, double>::value && rq.opts.precision == GSC_MIXED;
+        const double vec = (7.0 + (mx ? 1.5 : 0.0)) * NR * sizeof(cpx<T>);
+        const int M = (rq.proj ? rq.proj->M : 0) + 1;
+        const double KR = static_cast<double>(rq.K) * Rp;
+        return vec + KR * (9.0 * 16.0 + 2.0 * M * 16.0) + 64.0 * Rp * 64.0;
+    };
     const bool prof_was_on = ctx.prof.on;
     ctx.prof.on = false;   // no event nodes inside captured graphs
     gsc_status result = GSC_OK;
+    iters_out.assign(reqs.size(), 0);
+    std::vector<int> stream_busy(ns, 0);
+    double live_bytes = 0.0;            // workspaces held (live and finished, not yet released)
+    size_t next = 0, running = 0;
     try {
-        for (size_t j = 0; j < jobs.size(); ++j) {
+        // set-up of job j on stream si: workspace, first inner solve,
+        // captured chunk of graph_iters iterations
+        auto start = [&](size_t j, int si) {
             BatchJob &jb = jobs[j];
             SolveRequest &rq = *jb.req;
             Live &L = live[j];
             L.o = rq.opts;
-            hipStream_t st = streams[j % ns];
+            L.stream = si;
+            hipStream_t st = streams[si];
             std::vector<double> zh(rq.z, rq.z + 2 * rq.K);
             L.dz.alloc(rq.K);
             GSC_HIP(hipMemcpyAsync(L.dz.get(), zh.data(), zh.size() * sizeof(double), hipMemcpyHostToDevice, st));
@@ -2514,6 +2561,7 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
                                                    false);
             L.ts->set_stream(st);
             L.ts->allocate();
+            L.held = true;
             L.ts->init_phase(L.o, inner_tol, seed0);
             GSC_HIP(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
             L.dstat.alloc(1);
@@ -2523,15 +2571,75 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
                 capture(L, st);
                 L.graphed = true;
             }
-        }
-        // scheduler: keep one chunk in flight per job, poll completion events
-        size_t remaining = jobs.size();
-        while (remaining > 0) {
+        };
+        // outputs, statistics and handles of a finished job (its stream
+        // is idle); the workspace stays until its room is needed
+        auto finish = [&](size_t j) {
+            Live &L = live[j];
+            SolveRequest &rq = *jobs[j].req;
+            double *res_host = rq.stats ? rq.stats->res_recursive : nullptr;
+            unsigned char *conv_host = rq.stats ? rq.stats->converged : nullptr;
+            L.ts->write_outputs(rq.stats, res_host, conv_host, L.o.tol, rq.R);
+            iters_out[jobs[j].sys] = std::max(iters_out[jobs[j].sys], std::min(L.n, L.o.max_iter));
+            if (rq.stats) {
+                rq.stats->outer_iters = iters_out[jobs[j].sys];
+                rq.stats->inner_iters += L.ts->inner_total();
+                rq.stats->shift_rhs_iters += L.ts->shift_rhs_iters();
+                rq.stats->alg_bytes += L.bytes;
+                rq.stats->alg_bytes_inner += L.bytes_inner;
+            }
+            if (L.ts->worst_res() > L.o.tol || (L.ts->flags() & FLAG_INNER)) result = GSC_NOT_CONVERGED;
+            drop_handles(L);
+            L.finished = true;
+            stream_busy[L.stream] = 0;
+        };
+        while (next < jobs.size() || running > 0) {
             bool progress = false;
-            for (size_t j = 0; j < jobs.size(); ++j) {
+            // start the next jobs while a stream is free and their
+            // workspaces fit beside the ones held; finished jobs give back
+            // their room first (a job always starts when none is live)
+            while (next < jobs.size()) {
+                int si = -1;
+                for (int k = 0; k < ns; ++k)
+                    if (!stream_busy[k]) { si = k; break; }
+                if (si < 0) break;
+                const double need = job_bytes(jobs[next]);
+                if (live_bytes + need > budget) {
+                    for (size_t j = 0; j < next && live_bytes + need > budget; ++j)
+                        if (live[j].finished && live[j].held) {
+                            release_workspace(live[j]);
+                            live_bytes -= live[j].ws;
+                        }
+                }
+                if (running > 0 && live_bytes + need > budget) break;
+                live[next].ws = need;
+                live_bytes += need;
+                stream_busy[si] = 1;
+                ++running;
+                try {
+                    start(next, si);
+                } catch (const Error &e) {
+                    // the device is fuller than the estimate: with other
+                    // jobs live, undo this start and wait for their room
+                    if (e.code != GSC_E_NOMEM || running == 1) throw;
+                    (void)hipGetLastError();
+                    (void)hipStreamSynchronize(streams[si]);
+                    drop_handles(live[next]);
+                    release_workspace(live[next]);
+                    live_bytes -= need;
+                    budget = live_bytes;
+                    stream_busy[si] = 0;
+                    --running;
+                    break;
+                }
+                ++next;
+                progress = true;
+            }
+            // keep one chunk in flight per live job, poll completion events
+            for (size_t j = 0; j < next; ++j) {
                 Live &L = live[j];
                 if (L.finished) continue;
-                hipStream_t st = streams[j % ns];
+                hipStream_t st = streams[L.stream];
                 if (!L.inflight) {
                     if (L.graphed) {
                         GSC_HIP(hipGraphLaunch(L.exec, st));
@@ -2562,8 +2670,8 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
                 L.bytes += dci * L.ts->col_iter_bytes();
                 L.bytes_inner += dci * L.ts->col_iter_inner_bytes();
                 if (s.active_cols == 0 || L.n >= L.o.max_iter) {
-                    L.finished = true;
-                    --remaining;
+                    finish(j);
+                    --running;
                 } else if (L.o.inner_relax && L.ts->relax_from_status(s, L.graphed) && L.graphed) {
                     // the graph holds the Chebyshev step count: capture anew
                     (void)hipGraphExecDestroy(L.exec);
@@ -2576,44 +2684,17 @@ gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_it
             if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
         for (auto &st : streams) GSC_HIP(hipStreamSynchronize(st));
-        iters_out.assign(reqs.size(), 0);
-        for (size_t j = 0; j < jobs.size(); ++j) {
-            Live &L = live[j];
-            SolveRequest &rq = *jobs[j].req;
-            double *res_host = rq.stats ? rq.stats->res_recursive : nullptr;
-            unsigned char *conv_host = rq.stats ? rq.stats->converged : nullptr;
-            L.ts->write_outputs(rq.stats, res_host, conv_host, L.o.tol, rq.R);
-            iters_out[jobs[j].sys] = std::max(iters_out[jobs[j].sys], std::min(L.n, L.o.max_iter));
-            if (rq.stats) {
-                rq.stats->outer_iters = iters_out[jobs[j].sys];
-                rq.stats->inner_iters += L.ts->inner_total();
-                rq.stats->shift_rhs_iters += L.ts->shift_rhs_iters();
-                rq.stats->alg_bytes += L.bytes;
-                rq.stats->alg_bytes_inner += L.bytes_inner;
-            }
-            if (L.ts->worst_res() > L.o.tol || (L.ts->flags() & FLAG_INNER)) result = GSC_NOT_CONVERGED;
-        }
     } catch (...) {
         ctx.prof.on = prof_was_on;
         // other jobs' graphs and their status copies may still be in
         // flight: drain every stream before anything they use is released
         for (auto &st : streams) (void)hipStreamSynchronize(st);
-        for (auto &L : live) {
-            if (L.exec) (void)hipGraphExecDestroy(L.exec);
-            if (L.graph) (void)hipGraphDestroy(L.graph);
-            if (L.ev) (void)hipEventDestroy(L.ev);
-            if (L.hstat) (void)hipHostFree(L.hstat);
-        }
+        for (auto &L : live) drop_handles(L);
         for (auto &st : streams) (void)hipStreamDestroy(st);
         throw;
     }
     ctx.prof.on = prof_was_on;
-    for (auto &L : live) {
-        if (L.exec) (void)hipGraphExecDestroy(L.exec);
-        if (L.graph) (void)hipGraphDestroy(L.graph);
-        if (L.ev) (void)hipEventDestroy(L.ev);
-        if (L.hstat) (void)hipHostFree(L.hstat);
-    }
+    for (auto &L : live) drop_handles(L);
     for (auto &st : streams) (void)hipStreamDestroy(st);
     return result;
 }

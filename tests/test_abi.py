@@ -88,7 +88,7 @@ def test_option_defaults_and_binding():
     for f in ("fuse_steps", "rhs_tile", "recheck", "spmm_kernel", "inner_method", "graph_iters",
               "stream_hint", "cheb_block", "inner_relax"):
         assert getattr(o, f) == 0, f
-    assert o.batch_streams == 0 and list(o.reserved) == [0]
+    assert o.batch_streams == 0 and o.batch_mem_mb == 0 and o.row_groups == 0 and list(o.reserved) == [0]
     m = api.make_opts(tol=1e-6, fuse_steps=12, cheb_block=128, inner_relax=True, graph_iters=8,
                       precision="mixed", carry="projected")
     assert (m.tol, m.fuse_steps, m.cheb_block, m.inner_relax, m.graph_iters) == (1e-6, 12, 128, 1, 8)
@@ -96,3 +96,5 @@ def test_option_defaults_and_binding():
     assert api.make_opts(precision="c64").precision == _lib.C64
     assert list(m.reserved) == [0]
     assert api.make_opts(batch_streams=3).batch_streams == 3
+    b = api.make_opts(batch_mem_mb=512, row_groups=64)
+    assert (b.batch_mem_mb, b.row_groups) == (512, 64)

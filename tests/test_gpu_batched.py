@@ -129,3 +129,34 @@ def test_batched_relaxed_inner_tolerance(ctx):
         assert np.abs(o["q"].cpu().numpy() - q0).max() < 1e-10
         assert np.abs(o["e"].cpu().numpy() - e0).max() < 1e-9
         assert 0 < o["inner_iters"] < f["inner_iters"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_memory_budget_and_row_groups(ctx, precision):
+    """A budget of 1 MiB for the live jobs' workspaces (every job's is
+    larger) runs the jobs one at a time, each starting when the last has
+    finished and its workspace is released; caller row groups change the
+    product launches.  Both give the same G_jj, charges and energies as the
+    default schedule (every job's arithmetic is the same whatever runs
+    beside it: bit-identical), and the oracle's at the FP64 bar; a row-group
+    count that is not a multiple of 8 is rejected."""
+    from paper_1002_1202_amd import api, _lib
+    print(f"case: batched memory budget and row groups, {precision}", flush=True)
+    probs, refs = _problems(ctx)
+    base = api.solve_batched(ctx, probs, tol=1e-12, precision=precision)
+    tight = api.solve_batched(ctx, probs, tol=1e-12, precision=precision, batch_mem_mb=1)
+    rg = api.solve_batched(ctx, probs, tol=1e-12, precision=precision, row_groups=8, batch_mem_mb=1,
+                           batch_streams=2)
+    for b, t, o, (g0, q0, e0) in zip(base, tight, rg, refs):
+        assert t["outer_iters"] == b["outer_iters"]
+        assert bool((t["G_jj"] == b["G_jj"]).all())
+        assert bool((t["q"] == b["q"]).all()) and bool((t["e"] == b["e"]).all())
+        g = o["G_jj"].cpu().numpy()
+        err = np.abs(g - g0).max() / np.abs(g0).max()
+        print(f"  iters={o['outer_iters']} row_groups=8 err={err:.2e}", flush=True)
+        assert o["converged"].all()
+        assert err < 1e-10
+        assert np.abs(o["q"].cpu().numpy() - q0).max() < 1e-10
+    with pytest.raises(_lib.GscError) as ei:
+        api.solve_batched(ctx, probs[:1], tol=1e-6, row_groups=12)
+    assert ei.value.status == -1
