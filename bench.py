@@ -432,7 +432,7 @@ def charge_vjp_measure(ctx):
     return out
 
 
-def batched_compare(ctx, copy_gbs=None):
+def batched_compare(ctx, copy_gbs=None, tune=False):
     """The 32-system batched workload (projected carry: G_jj, charges and
     band-energy terms) at the workloads' tol 1e-6, timed for the mixed and
     the plain FP64 solver, each with and without the relaxed inner
@@ -442,7 +442,9 @@ def batched_compare(ctx, copy_gbs=None):
     the dense-LU oracle on sampled shifts of the systems with N <= 8192.
     Speed-ups are stated only between runs that meet 1e-6 on G_jj and
     1e-5 e on the charges.  Algorithmic bytes come from the library's count
-    of column-iterations (no events inside the captured graphs)."""
+    of column-iterations (no events inside the captured graphs).  With
+    ``tune`` the autotuner first searches the batch's tile and launch shapes
+    for the mixed solver, and the mixed runs are repeated with them."""
     import numpy as np
     import torch
 
@@ -462,17 +464,20 @@ def batched_compare(ctx, copy_gbs=None):
     if copy_gbs is None:
         copy_gbs = copy_bandwidth()
 
-    def run(prec, tol=1e-6, relax=False):
+    def run(prec, tol=1e-6, relax=False, shapes=None):
+        shapes = dict(shapes or {})
+        shapes.setdefault("graph_iters", 4)
         api.solve_batched(ctx, probs[:2], tol=tol, precision=prec, max_iter=4, inner_relax=relax)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        o = api.solve_batched(ctx, probs, tol=tol, precision=prec, graph_iters=4, inner_relax=relax)
+        o = api.solve_batched(ctx, probs, tol=tol, precision=prec, inner_relax=relax, **shapes)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         work = sum(x["shift_rhs_iters"] for x in o)
         by = sum(x["alg_bytes"] for x in o)
         bi = sum(x["alg_bytes_inner"] for x in o)
-        rec = {"precision": prec, "tol": tol, "inner_relax": relax, "seconds": dt, "value": work / dt,
+        rec = {"precision": prec, "tol": tol, "inner_relax": relax, "shapes": shapes, "seconds": dt,
+               "value": work / dt,
                "unit": UNIT, "max_outer_iters": max(x["outer_iters"] for x in o),
                "inner_steps": sum(x["inner_iters"] for x in o),
                "converged_frac": float(np.mean([x["converged"].mean() for x in o])),
@@ -485,9 +490,18 @@ def batched_compare(ctx, copy_gbs=None):
         return rec, [(x["G_jj"].cpu().numpy(), x["q"].cpu().numpy(), x["e"].cpu().numpy()) for x in o]
 
     runs = {}
-    for name, prec, relax in (("mixed", "mixed", False), ("mixed_relax", "mixed", True),
-                              ("fp64", "fp64", False), ("fp64_relax", "fp64", True), ("c64", "c64", False)):
-        runs[name] = run(prec, relax=relax)
+    plan = [("mixed", "mixed", False, None), ("mixed_relax", "mixed", True, None),
+            ("fp64", "fp64", False, None), ("fp64_relax", "fp64", True, None), ("c64", "c64", False, None)]
+    if tune:
+        from paper_1002_1202_amd import autotune
+        t0 = time.perf_counter()
+        best = autotune.tune_batched(ctx, probs, precision="mixed", tol=1e-6, force=True, verbose=True)
+        out["autotune"] = {"shapes": best, "seconds": time.perf_counter() - t0,
+                           "space": autotune.SPACE_BATCHED}
+        print(f"batched autotune: {best}", file=sys.stderr, flush=True)
+        plan += [("mixed_tuned", "mixed", False, best), ("mixed_relax_tuned", "mixed", True, best)]
+    for name, prec, relax, shapes in plan:
+        runs[name] = run(prec, relax=relax, shapes=shapes)
     ref_rec, ref = run("fp64", tol=1e-10)
     out["reference"] = ref_rec
     # the reference against the dense-LU oracle on 4 sampled shifts of the
@@ -518,6 +532,11 @@ def batched_compare(ctx, copy_gbs=None):
         "mixed_relax_vs_fp64_relax": (sec["fp64_relax"] / sec["mixed_relax"]
                                       if ok["mixed_relax"] and ok["fp64_relax"] else None),
         "mixed_relax_vs_plain_fp64": sec["fp64"] / sec["mixed_relax"] if ok["mixed_relax"] and ok["fp64"] else None}
+    if tune:
+        out["speedup_at_1e-6"].update({
+            "mixed_tuned_vs_fp64": sec["fp64"] / sec["mixed_tuned"] if ok["mixed_tuned"] and ok["fp64"] else None,
+            "mixed_relax_tuned_vs_plain_fp64": (sec["fp64"] / sec["mixed_relax_tuned"]
+                                                if ok["mixed_relax_tuned"] and ok["fp64"] else None)})
     return out
 
 
@@ -637,7 +656,7 @@ def main():
                                         inner_relax=args.forces_inner_relax)), flush=True)
         return
     if args.only == "batched":
-        print(json.dumps(batched_compare(api.Context(0))), flush=True)
+        print(json.dumps(batched_compare(api.Context(0), tune=args.autotune)), flush=True)
         return
     if args.only == "member":
         print(json.dumps(member_measure(api.Context(0), args.member, args.precision, tol=args.tol or 1e-6)),
@@ -774,7 +793,7 @@ def main():
         line["charge_vjp"] = charge_vjp_measure(ctx)
         print(f"charge_vjp: {line['charge_vjp']}", file=sys.stderr, flush=True)
     if not args.no_batched:
-        line["batched"] = batched_compare(ctx, copy_gbs)
+        line["batched"] = batched_compare(ctx, copy_gbs, tune=args.autotune)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters)
         print(f"cpu baseline: {line['cpu_baseline']['sample']}", file=sys.stderr, flush=True)
