@@ -238,6 +238,10 @@ gsc_status gsc_pair_set_values(gsc_pair *pair, const double *Hval, const double 
 gsc_status gsc_pair_get_values(const gsc_pair *pair, double *Hval, double *Sval, int mem);
 /* Sizes: N, nnzb, block. */
 gsc_status gsc_pair_info(const gsc_pair *pair, int64_t *n, int64_t *nnzb, int *block);
+/* Frees the pair.  Every other call on a pair needs its context alive; the
+ * destruction does not, so pairs and contexts may be destroyed in either
+ * order (garbage collectors finalise unreachable objects in any order).
+ * The same holds for gsc_csc_destroy. */
 void gsc_pair_destroy(gsc_pair *pair);
 
 /* ---- ASED pair (Sec. 2.2, eq. Hap-1) ------------------------------------- */

@@ -306,6 +306,7 @@ gsc_status gsc_pair_create(gsc_ctx *ctx, int block, int64_t nbrows, const int64_
         DeviceGuard g(ctx->c.device);
         auto p = std::make_unique<gsc_pair>();
         p->p.ctx = &ctx->c;
+        p->p.device = ctx->c.device;
         validate_and_upload(p->p, block, nbrows, rowptr, colidx);
         if (Hval || Sval) set_values(p->p, Hval, Sval, mem);
         *out = p.release();
@@ -346,13 +347,16 @@ gsc_status gsc_pair_info(const gsc_pair *pair, int64_t *n, int64_t *nnzb, int *b
     });
 }
 
+// destruction reads the device ordinal kept in the object, never the
+// context, which may already be gone
 void gsc_pair_destroy(gsc_pair *pair) {
     if (!pair) return;
     int prev = -1;
-    (void)hipGetDevice(&prev);
-    (void)hipSetDevice(pair->p.ctx->device);
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    const int dev = pair->p.device;
+    if (prev != dev) (void)hipSetDevice(dev);
     delete pair;
-    if (prev >= 0) (void)hipSetDevice(prev);
+    if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
 }
 
 gsc_status gsc_ased_build(gsc_ctx *ctx, const gsc_ased_geom *geom, double scale, gsc_pair *pair,
@@ -695,8 +699,12 @@ gsc_status gsc_csc_create(gsc_ctx *ctx, const gsc_pair *pair, const gsc_ased_geo
 
 void gsc_csc_destroy(gsc_csc *csc) {
     if (csc == nullptr) return;
-    DeviceGuard g(csc->c.ctx->device);
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    const int dev = csc->c.device;
+    if (prev != dev) (void)hipSetDevice(dev);
     delete csc;
+    if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
 }
 
 gsc_status gsc_csc_potential(gsc_csc *csc, const double *dq, double *V, int mem) {

@@ -156,6 +156,7 @@ struct Ctx {
 
 struct Pair {
     Ctx *ctx = nullptr;
+    int device = 0;             // the context's device (destruction does not read ctx)
     int B = 4;
     int64_t nb = 0, n = 0, nnzb = 0;
     DevBuf<int32_t> rowptr;     // nb+1

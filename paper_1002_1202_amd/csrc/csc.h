@@ -9,6 +9,7 @@ namespace gsc {
 // their interaction gamma, and the atom -> orbital map.
 struct Csc {
     Ctx *ctx = nullptr;
+    int device = 0;             // the context's device (destruction does not read ctx)
     int64_t n_atoms = 0, npairs = 0;
     int B = 0;
     int64_t N = 0, nnzb = 0;

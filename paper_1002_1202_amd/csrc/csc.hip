@@ -122,6 +122,7 @@ inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + 255) /
 
 void csc_build(Csc &c, Ctx &ctx, const Pair &p, const gsc_ased_geom &g, const double *U) {
     c.ctx = &ctx;
+    c.device = ctx.device;
     c.n_atoms = g.n_atoms;
     c.B = p.B;
     c.N = p.n;

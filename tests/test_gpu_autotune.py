@@ -31,7 +31,10 @@ def test_tune_solve_caches_and_keeps_parity(tmp_path, monkeypatch):
     data = json.loads(cache.read_text())
     key = autotune.shape_key(pair.block, pair.n, len(rhs), len(z), "fp64", "full")
     assert data[key]["opts"] == best
-    assert sum(np.isfinite(t["ms_per_iter"]) for t in data[key]["trials"]) == 4
+    # one trial per option set of the coordinate search (1 + one per knob);
+    # a trial whose two lengths do not separate counts as infinitely slow
+    assert len(data[key]["trials"]) == 4
+    assert any(np.isfinite(t["ms_per_iter"]) for t in data[key]["trials"])
     # second call: from the cache
     assert autotune.tune_solve(ctx, pair, z, rhs, tol=1e-10, space=space) == best
     sub = rhs[:6]
@@ -63,13 +66,14 @@ def test_tune_batched_tile_shapes_cache_and_parity(tmp_path, monkeypatch):
         probs.append(dict(pair=pair, z=c["z"], rhs=c["rhs"]))
     print(f"case: tune_batched {[p['pair'].n for p in probs]}", flush=True)
     space = {"graph_iters": [0, 1], "batch_streams": [0, 2], "rhs_tile": [0, 64], "row_groups": [0, 64]}
-    best = autotune.tune_batched(ctx, probs, precision="fp64", tol=1e-10, t1=4, t2=12, space=space, force=True)
+    best = autotune.tune_batched(ctx, probs, precision="fp64", tol=1e-10, t1=4, t2=24, space=space, force=True)
     print(f"  best {best}", flush=True)
     assert all(k in space and v in space[k][1:] for k, v in best.items())
     data = json.loads(cache.read_text())
     key = autotune.batch_key(probs, "fp64")
     assert data[key]["opts"] == best
-    assert sum(np.isfinite(t["ms_per_iter"]) for t in data[key]["trials"]) == 5
+    assert len(data[key]["trials"]) == 5
+    assert any(np.isfinite(t["ms_per_iter"]) for t in data[key]["trials"])
     assert autotune.tune_batched(ctx, probs, precision="fp64", space=space) == best
     outs = api.solve_batched(ctx, probs, tol=1e-12, **best)
     for c, o in zip(cases, outs):

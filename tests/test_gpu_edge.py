@@ -270,3 +270,29 @@ def test_breakdown_status(ctx, prec, carry):
     res = api.solve(ctx, pair, z, B=good, tol=1e-12, precision=prec)
     ref = good[0][None, :] / (z[:, None] - eps[None, :])
     assert rel(res.G_cols[:, 0, :], ref) < 1e-11
+
+
+def test_objects_outlive_their_context():
+    """A pair and a CSC object destroyed after their context (the order a
+    garbage collector may choose) free cleanly and leave no error behind:
+    the next context solves as usual."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1002_1202_amd import api
+    from synth.csc import hubbard_u
+    print("case: pair and CSC object destroyed after their context", flush=True)
+    c = configs.water_small(n_mol=4, n_rhs=4)
+    s = c["system"]
+    ctx1 = api.Context(0)
+    pair1, _ = api.pair_from_system(ctx1, s)
+    csc1 = api.Csc(ctx1, pair1, s, hubbard_u(s))
+    ctx1.close()
+    csc1.__del__()
+    pair1.close()
+    ctx2 = api.Context(0)
+    pair2, _ = api.pair_from_system(ctx2, s)
+    res = api.solve(ctx2, pair2, c["z"], rhs=c["rhs"], tol=1e-12)
+    S, H, _ = oased.dense_pair(s)
+    X = ogreen.solve_dense(H, S, c["z"], c["rhs"])
+    assert res.status == 0 and rel(res.G_cols, X) < 1e-10
