@@ -641,18 +641,31 @@ void launch_mx_resid(hipStream_t st, const Pair &pr, const TileDims &td, int col
 
 // ------------------------------------------------------------------ launchers
 // Row-group geometry of the product kernels (td.Gs row groups; every
-// reduction of their partials uses td.Gs).  One block row per wave where the
-// rows allow: the rows a sweep keeps in flight then span few x-planes, whose
-// halo fits L2.  With more than 8 column chunks an XCD would run the row
-// groups of several chunks at once (each with its own x window) unless the
-// groups of one chunk fill it: at least 256 groups then.
+// reduction of their partials uses td.Gs).  One block row per wave whenever
+// the launch stays within 16384 workgroups: the rows a sweep keeps in flight
+// then span few x-planes, whose halo fits L2, and no wave takes a second row
+// while most take one (with 4096 groups over 4760 row slots, a 64-column
+// launch on N = 76152 took 28 % longer than with one row each).  Wider
+// launches keep about 4096 workgroups, at least 256 groups when there are
+// more than 8 column chunks (an XCD would otherwise run the groups of
+// several chunks at once, each with its own x window), and the groups are
+// sized so that every wave takes the same number of rows.
 void set_spmm_geometry(TileDims &td, const Pair &pr) {
     (void)pr;
     const int w = td.cb > 0 && td.cb < td.Rp ? td.cb : td.Rp;   // width of a Chebyshev launch
-    int g = std::max(1, 4096 / std::max(1, w / 64));
-    if (w / 64 > 8) g = std::max(g, 256);
-    g = static_cast<int>(std::min<int64_t>(g, (td.nb + 3) / 4));
-    td.Gs = (std::max(g, 1) + 7) / 8 * 8;
+    const int chunks = std::max(1, w / 64);
+    const int64_t slots = std::max<int64_t>(1, (td.nb + 3) / 4);   // groups for one row per wave
+    int64_t g;
+    if (chunks * slots <= 16384) {
+        g = slots;
+    } else {
+        int64_t g0 = std::max(1, 4096 / chunks);
+        if (chunks > 8) g0 = std::max<int64_t>(g0, 256);
+        g0 = std::min(g0, slots);
+        const int64_t passes = (slots + g0 - 1) / g0;
+        g = (slots + passes - 1) / passes;
+    }
+    td.Gs = static_cast<int>((std::min<int64_t>(g, 65528) + 7) / 8 * 8);
 }
 
 template <typename T>
