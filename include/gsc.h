@@ -93,7 +93,8 @@ typedef struct {
                               carry), 1..16                                    */
     int rhs_tile;          /* [0 = auto] right-hand sides per device tile      */
     int recheck;           /* [0] 1: FP64 true residual of every (k, rhs) into
-                              gsc_stats.res_true (full carry only)             */
+                              gsc_stats.res_true (full carry only: the
+                              projected carry keeps no x_k to check)          */
     int spmm_kernel;       /* [0 = auto = 1] product kernel layout: 1 one block
                               row x 64 rhs per wave (the complex64 steps of
                               GSC_MIXED: 128 rhs per wave, two per lane)      */
@@ -142,8 +143,10 @@ typedef struct {
                               80 % of the device memory free at the call.    */
     int row_groups;        /* [0 = auto] workgroup rows of the product and
                               Chebyshev launches (a multiple of 8, at most
-                              65528; capped at one block row per wave);
-                              auto from the launch width                      */
+                              65528; capped at one block row per wave); auto:
+                              one block row per wave while a launch stays
+                              within 16384 workgroups, else about 4096
+                              workgroups with equal rows per wave             */
     int reserved[1];
 } gsc_opts;
 
