@@ -33,6 +33,14 @@
  *    GSC_NOT_CONVERGED is positive: all outputs are written, together with
  *    per-(shift, rhs) residual estimates and convergence flags in gsc_stats.
  *    Arguments are validated before any device work is launched.
+ *  - Results are deterministic: the same inputs and options on the same
+ *    device give bitwise-equal outputs, whatever else runs beside them
+ *    (every reduction sums its partials in a fixed order; no floating-point
+ *    atomics).  Options that change the launch shapes (rhs_tile, cheb_block,
+ *    row_groups, fuse_steps) change the summation order and so the last
+ *    bits; gsc_solve_batched's scheduling options (batch_streams,
+ *    batch_mem_mb, graph_iters) do not (graph_iters only rounds the
+ *    reported iteration count up to whole chunks).
  */
 #ifndef GSC_H
 #define GSC_H
