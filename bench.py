@@ -344,15 +344,16 @@ def lanczos_compare(ctx, cfg):
 
 
 def scc_measure(ctx):
-    """Charge self-consistency (eq. Hap-CSC): a converging small water box end
-    to end, and the cost of one iteration (charges of every orbital by the
-    projected solve + CSC update) on a larger box.  The Fermi level sits
-    mid-gap of the neutral system (from the oracle's spectrum of the small
-    box; the larger box uses the same value)."""
+    """Charge self-consistency (eq. Hap-CSC) end to end on small water boxes:
+    8 molecules with a fixed integration window (E_F mid-gap of the neutral
+    system, from the oracle's spectrum) and 24 molecules with E_F set each
+    iteration by charge neutrality; both converge to 1e-9 e.  The oracle's
+    loops (dense LU per shift, 1 thread) are timed beside them."""
     import numpy as np
     import torch
+    from threadpoolctl import threadpool_limits
 
-    from oracle import ased as oased, spectral as ospec
+    from oracle import ased as oased, csc as ocsc, spectral as ospec
     from paper_1002_1202_amd import api
     from synth import configs
     from synth.csc import hubbard_u
@@ -360,35 +361,39 @@ def scc_measure(ctx):
 
     out = {}
     small = configs.water_small(n_mol=8, n_rhs=4)["system"]
-    S, H0, _ = oased.dense_pair(small)
-    ev, _ = ospec.eig_pencil(H0, S)
+    S8, H8, _ = oased.dense_pair(small)
+    ev, _ = ospec.eig_pencil(H8, S8)
     nocc = int(round(small.valence.sum() / 2))
     ef = 0.5 * (ev[nocc - 1] + ev[nocc])
-    z = shift_grid(-60.0, ef, 128, 0.5)
-    w = trapezoid_weights(z)
-    for name, n_mol, iters in (("water8", 8, 200), ("water256", 256, 3)):
+    z_fixed = shift_grid(-60.0, ef, 128, 0.5)
+    z_neutral = shift_grid(-60.0, 5.0, 128, 0.5)
+    runs = (("water8_fixed_window", 8, z_fixed, trapezoid_weights(z_fixed), False, 4),
+            ("water24_neutral", 24, z_neutral, None, True, 6))
+    for name, n_mol, z, w, neutral, hist in runs:
         s = small if n_mol == 8 else configs.water_small(n_mol=n_mol, n_rhs=4)["system"]
         pair, _ = api.pair_from_system(ctx, s)
         cs = api.Csc(ctx, pair, s, hubbard_u(s))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = cs.scc(pair, z, w, s.valence, beta=0.2, history=4, scc_tol=1e-9, max_iter=iters, tol=1e-10)
+        r = cs.scc(pair, z, w, s.valence, beta=0.2, history=hist, scc_tol=1e-9, max_iter=300, tol=1e-10,
+                   neutral=neutral)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        out[name] = {"atoms": int(s.n_atoms), "N": int(s.n), "shifts": int(len(z)), "iterations": r["iterations"],
-                     "residual": r["residual"], "seconds": dt, "seconds_per_iteration": dt / r["iterations"],
-                     "converged": r["status"] == 0}
-    # the oracle's loop (dense LU per shift), 1 thread, on the small box
-    from threadpoolctl import threadpool_limits
-
-    from oracle import csc as ocsc
-    gamma = ocsc.gamma_matrix(small, hubbard_u(small))
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        _, _, _, it_or, _ = ocsc.scc(small, S, H0, gamma, z, w, beta=0.2, tol=1e-9, max_iter=200, history=4)
-        t_or = time.perf_counter() - t0
-    out["cpu_oracle_water8"] = {"kind": "oracle", "cores": 1, "seconds": t_or, "iterations": it_or,
-                                "seconds_per_iteration": t_or / max(it_or, 1)}
+        rec = {"atoms": int(s.n_atoms), "N": int(s.n), "shifts": int(len(z)), "neutral": neutral,
+               "iterations": r["iterations"], "residual": r["residual"], "seconds": dt,
+               "seconds_per_iteration": dt / r["iterations"], "converged": r["status"] == 0}
+        if neutral:
+            rec["e_fermi"] = r["e_fermi"]
+        S, H0, _ = oased.dense_pair(s)
+        gamma = ocsc.gamma_matrix(s, hubbard_u(s))
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            ref = ocsc.scc(s, S, H0, gamma, z, w, beta=0.2, tol=1e-9, max_iter=300, history=hist,
+                           neutral=neutral)
+            t_or = time.perf_counter() - t0
+        rec["dq_max_diff_vs_oracle"] = float(np.abs(r["dq"] - ref[0]).max())
+        rec["cpu_oracle"] = {"kind": "oracle", "cores": 1, "seconds": t_or, "iterations": ref[3]}
+        out[name] = rec
     return out
 
 
