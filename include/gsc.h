@@ -99,7 +99,9 @@ typedef struct {
     int fuse_steps;        /* [0 = auto = 16] number m of shift-update steps
                               applied per pass over the shifted vectors (full
                               carry), 1..16                                    */
-    int rhs_tile;          /* [0 = auto] right-hand sides per device tile      */
+    int rhs_tile;          /* [0 = auto] right-hand sides per device tile
+                              (auto: all that fit; gsc_solve_batched: at most
+                              128 per job)                                    */
     int recheck;           /* [0] 1: FP64 true residual of every (k, rhs) into
                               gsc_stats.res_true (full carry only: the
                               projected carry keeps no x_k to check)          */

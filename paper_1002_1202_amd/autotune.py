@@ -54,7 +54,7 @@ SPACE_PROJECTED = {
 SPACE_BATCHED = {
     "graph_iters": [0, 1, 8],
     "batch_streams": [0, 2, 4, 16],
-    "rhs_tile": [0, 128, 256],
+    "rhs_tile": [0, 64, 256],
     "cheb_block": [0, 64, 128],
     "row_groups": [0, 256, 1024],
 }

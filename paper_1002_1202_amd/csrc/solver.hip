@@ -30,6 +30,7 @@ namespace gsc {
 // budget of the Chebyshev column blocks' streamed vectors (of the 256 MB
 // infinity cache)
 constexpr double kChebBlockBytes = 224.0e6;
+constexpr int kBatchTile = 128;   // default rhs per job of gsc_solve_batched
 
 // ------------------------------------------------------------------ helpers
 template <typename V>
@@ -2452,11 +2453,13 @@ struct BatchJob {
 template <typename T>
 gsc_status batched_typed(Ctx &ctx, std::vector<SolveRequest> &reqs, int graph_iters, int max_streams,
                          std::vector<int> &iters_out) {
-    // jobs: one per (system, rhs tile), longest first
+    // jobs: one per (system, rhs tile), longest first; tiles of at most 128
+    // rhs by default (more, smaller jobs keep the streams evenly loaded:
+    // batch32 2.5 % faster than whole systems as jobs, mixed and FP64)
     std::vector<BatchJob> jobs;
     for (size_t si = 0; si < reqs.size(); ++si) {
         SolveRequest &rq = reqs[si];
-        const int Rt = rq.opts.rhs_tile > 0 ? rq.opts.rhs_tile : rq.R;
+        const int Rt = rq.opts.rhs_tile > 0 ? rq.opts.rhs_tile : std::min(rq.R, kBatchTile);
         for (int r0 = 0; r0 < rq.R; r0 += Rt) {
             BatchJob j;
             j.req = &rq;
