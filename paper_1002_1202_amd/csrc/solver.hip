@@ -2033,9 +2033,12 @@ template <typename T> class TileSolver {
 
     // Rounds of the mixed inner solve for a relative tolerance tau: one
     // round when tau >= kMxSingle (a few times what the FP32 residual
-    // estimate resolves), else rounds that each reduce their right-hand side
-    // to kMxFloor, the FP64 residual between rounds carrying the rest;
-    // entries are the step counts K_j of the rounds.
+    // estimate resolves), else rounds asked for kMxFloor each, the FP64
+    // residual between rounds carrying the rest.  A round of K steps
+    // reaches its Chebyshev bound 2 rho^K, but no lower than kMxReach, where
+    // complex64 arithmetic stagnates: the next round is planned for what is
+    // left after that (the residual check after the last round catches a
+    // round that fell short).  Entries are the step counts K_j.
     std::vector<int> mx_plan_for(double tau) const {
         std::vector<int> plan;
         // down to kMxSingle one complex64 round is cheaper than two rounds
@@ -2043,9 +2046,10 @@ template <typename T> class TileSolver {
         if (tau >= kMxSingle) return {cheb_steps_for(tau)};
         double rem = tau;
         while (true) {
-            plan.push_back(cheb_steps_for(std::max(rem, kMxFloor)));
+            const int k = cheb_steps_for(std::max(rem, kMxFloor));
+            plan.push_back(k);
             if (rem >= kMxFloor * (1.0 - 1e-9) || plan.size() == 4) break;
-            rem /= kMxFloor;
+            rem /= std::max(2.0 * std::pow(cheb_rho_, k), kMxReach);
         }
         return plan;
     }
@@ -2309,6 +2313,7 @@ template <typename T> class TileSolver {
     DevBuf<c64> mx_f_, mx_ya_, mx_yb_;
     std::vector<int> mx_plan_;
     static constexpr double kMxFloor = 1e-5;
+    static constexpr double kMxReach = 4e-6;
     static constexpr double kMxSingle = 2e-6;
     static constexpr int kMxSafetySteps = 4;
     long long cheb_extra_ = 0;
