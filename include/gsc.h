@@ -134,7 +134,7 @@ typedef struct {
                               anew when its step count changes): each outer
                               iteration solves S r' = r to inner_tol divided
                               by the largest residual among the shifts still
-                              above tol (at most 1e-4, at least inner_tol),
+                              above tol (at most 1e-3, at least inner_tol),
                               so the inner error that reaches every
                               unconverged shift stays at inner_tol relative
                               to ||b||.  0 keeps the fixed inner_tol of the

@@ -2304,7 +2304,7 @@ template <typename T> class TileSolver {
     double cheb_theta_ = 1.0, cheb_delta_ = 0.5, cheb_rho_ = 0.5, cheb_lo_ = 0.0, cheb_hi_ = 0.0;
     int cheb_steps_ = 0, cheb_max_ = 200;
     double inner_tol_base_ = 0.0;     // the fixed inner tolerance of the solve
-    static constexpr double kRelaxCap = 1e-4;
+    static constexpr double kRelaxCap = 1e-3;
     // mixed inner solve: precision flag, complex64 right-hand side (r after
     // each residual update, or the FP64 residual between rounds) and the two
     // alternating complex64 iterates; the plan of rounds
