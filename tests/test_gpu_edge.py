@@ -296,3 +296,22 @@ def test_objects_outlive_their_context():
     S, H, _ = oased.dense_pair(s)
     X = ogreen.solve_dense(H, S, c["z"], c["rhs"])
     assert res.status == 0 and rel(res.G_cols, X) < 1e-10
+
+
+@pytest.mark.parametrize("groups", [8, 64, 65528])
+def test_row_groups_option(ctx, groups):
+    """Caller row groups for the product and Chebyshev launches: many rows
+    per wave (8 groups), a few (64), and more than the rows need (capped at
+    one row per wave), full and projected carry against the dense LU."""
+    from paper_1002_1202_amd import api
+    print(f"case: row_groups={groups}", flush=True)
+    c = configs.si_small(cells=(3, 3, 2), n_shift=12, eta=0.1, n_rhs=70, seed=71, vacancy_frac=0.02)
+    s, z, rhs = c["system"], c["z"], c["rhs"]
+    S, H, _ = oased.dense_pair(s)
+    X = ogreen.solve_dense(H, S, z, rhs)
+    pair, _ = api.pair_from_system(ctx, s)
+    res = api.solve(ctx, pair, z, rhs=rhs, tol=1e-12, row_groups=groups)
+    assert res.status == 0 and rel(res.G_cols, X) < 1e-10
+    resp = api.solve(ctx, pair, z, rhs=rhs, tol=1e-12, row_groups=groups, carry="projected",
+                     proj=np.asarray(rhs)[:, None], precision="mixed")
+    assert rel(resp.G_proj[:, :, 0], X[:, np.arange(len(rhs)), rhs]) < 1e-10
